@@ -1,0 +1,260 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by the mathematics (CPU only).
+
+Each test would fail for a plausible mistake in the oracle: a dropped autocorrelation or a wrong conjugation
+(FX identity), a wrong DFT sign or pixel axis (lone point source, numpy ifft2 reduction), a wrong
+normalisation (Parseval), a mirrored image or swapped products (invariants).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import moff_oracle as ora
+from paper_0812_3669_amd import configs, synth
+from tests.fx_pin import direct_imaging, fx_image
+
+pytestmark = pytest.mark.filterwarnings("ignore::DeprecationWarning")
+
+
+def _origin(ant_xy, f, cell, n, K):
+    # independent recompute of the footprint convention: cells floor(X)-K/2+1 .. floor(X)+K/2
+    X = ant_xy[:, 0] * f / configs.C_LIGHT / cell + n / 2
+    Y = ant_xy[:, 1] * f / configs.C_LIGHT / cell + n / 2
+    return np.stack([np.floor(Y).astype(int) - K // 2 + 1, np.floor(X).astype(int) - K // 2 + 1], axis=1)
+
+
+def _small(P, A=24, n=32, T=8, K=4, seed=7, disk=14.0):
+    cfg = configs.scaled(configs.TINY, index=50 + seed, n_ant=A, n_pol=P, grid_n=n, n_time=T, ksize=K,
+                         disk_lambda=disk, int8=(P == 2))
+    geo = synth.geometry(cfg)
+    g = synth.gains(cfg)
+    sk = synth.sky(cfg)
+    kern = synth.kernels(geo, g, P)
+    volts = synth.voltages_host(cfg, geo, g, sk)
+    return cfg, geo, kern, volts
+
+
+def _peak_err(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+# ---------------------------------------------------------------------------------------------------------
+# 1. FX brute force (Eqs. visDef, Bdef, m1-m6): MOFF image == software-holography image of all visibilities
+# ---------------------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("P", [1, 2])
+def test_fx_identity(P):
+    cfg, geo, kern, volts = _small(P)
+    img = ora.image(volts, kern, geo.ant_xy_m, geo.freqs_hz, geo.grid_n, cfg.cell_lambda)[0]
+    e = ora.unpack(volts)[:, 0]                                                # [T, A, P]
+    origin = _origin(geo.ant_xy_m, geo.freqs_hz[0], cfg.cell_lambda, cfg.grid_n, cfg.ksize)
+    fx = fx_image(e, kern[0], origin, cfg.grid_n)
+    for k in range(img.shape[0]):
+        assert _peak_err(img[k], fx[k]) < 1e-12, k
+
+
+def test_fx_identity_k6_odd_sizes():
+    cfg, geo, kern, volts = _small(2, A=13, n=40, T=5, K=6, seed=3, disk=20.0)
+    img = ora.image(volts, kern, geo.ant_xy_m, geo.freqs_hz, geo.grid_n, cfg.cell_lambda)[0]
+    origin = _origin(geo.ant_xy_m, geo.freqs_hz[0], cfg.cell_lambda, cfg.grid_n, cfg.ksize)
+    fx = fx_image(ora.unpack(volts)[:, 0], kern[0], origin, cfg.grid_n)
+    for k in range(4):
+        assert _peak_err(img[k], fx[k]) < 1e-12
+
+
+def test_fx_identity_catches_dropped_autocorrelations():
+    """A plausible oracle mistake (only cross pairs) is far outside the FX pin's tolerance."""
+    cfg, geo, kern, volts = _small(1)
+    img = ora.image(volts, kern, geo.ant_xy_m, geo.freqs_hz, geo.grid_n, cfg.cell_lambda)[0]
+    e = ora.unpack(volts)[:, 0]
+    origin = _origin(geo.ant_xy_m, geo.freqs_hz[0], cfg.cell_lambda, cfg.grid_n, cfg.ksize)
+    auto_only = np.zeros_like(e)
+    auto_only[:, 0] = e[:, 0]
+    # the single-antenna image is the autocorrelation term of antenna 0; removing it changes the image
+    fx_auto = fx_image(auto_only, kern[0], origin, cfg.grid_n)
+    assert np.abs(fx_auto).max() / np.abs(img).max() > 1e-3
+
+
+# ---------------------------------------------------------------------------------------------------------
+# 2. Parseval: the DFT normalisation (sum over pixels = n^2 * grid energy)
+# ---------------------------------------------------------------------------------------------------------
+def test_parseval():
+    cfg, geo, kern, volts = _small(2, T=6)
+    n, K = cfg.grid_n, cfg.ksize
+    img = ora.image(volts, kern, geo.ant_xy_m, geo.freqs_hz, geo.grid_n, cfg.cell_lambda)[0]
+    origin = ora.footprint_origin(geo.ant_xy_m, geo.freqs_hz[0], cfg.cell_lambda, n, K)
+    e = ora.unpack(volts)[:, 0]
+    G = [ora.grid_many(e[:, :, p], kern[0, :, p], origin, n) for p in range(2)]
+    assert abs(img[0].sum() - n * n * np.sum(np.abs(G[0]) ** 2)) / abs(img[0].sum()) < 1e-12
+    assert abs(img[1].sum() - n * n * np.sum(np.abs(G[1]) ** 2)) / abs(img[1].sum()) < 1e-12
+    cross = n * n * np.sum(G[0] * np.conj(G[1]))
+    assert abs(img[2].sum() - cross) / abs(img[0].sum()) < 1e-12
+
+
+def test_grid_many_matches_scatter():
+    cfg, geo, kern, volts = _small(2, T=3)
+    origin = ora.footprint_origin(geo.ant_xy_m, geo.freqs_hz[0], cfg.cell_lambda, cfg.grid_n, cfg.ksize)
+    e = ora.unpack(volts)[:, 0]
+    Gm = ora.grid_many(e[:, :, 1], kern[0, :, 1], origin, cfg.grid_n)
+    for t in range(3):
+        Gs = ora.grid(e[t, :, 1], kern[0, :, 1], origin, cfg.grid_n)
+        assert np.abs(Gm[t] - Gs).max() < 1e-12 * np.abs(Gs).max()
+
+
+# ---------------------------------------------------------------------------------------------------------
+# 3. Lone point source: sign of the imaging transform, kernel conjugation and pixel axes
+# ---------------------------------------------------------------------------------------------------------
+def _lone_source_delta(n=32, A=10, T=4, dq=(-3, 5), seed=1):
+    """Delta kernels (one unit tap at (K/2-1, K/2-1)), antennas on integer cells, unit gains, no noise."""
+    rng = np.random.default_rng(seed)
+    K, cell, f = 4, 1.0, configs.C_LIGHT      # f = c -> one metre is one wavelength
+    cells = rng.choice(np.arange(8, n - 8), size=(A, 2))
+    ant_xy = np.stack([cells[:, 1] - n / 2, cells[:, 0] - n / 2], axis=1).astype(np.float64)  # x=east, y=north
+    qs, ps = n // 2 + dq[0], n // 2 + dq[1]
+    l_s, m_s = (ps - n / 2) / (n * cell), (qs - n / 2) / (n * cell)
+    s = rng.standard_normal(T) + 1j * rng.standard_normal(T)
+    e = s[:, None] * np.exp(-2j * np.pi * (ant_xy[:, 0] * l_s + ant_xy[:, 1] * m_s))[None, :]
+    kern = np.zeros((1, A, 1, K, K), dtype=np.complex64)
+    kern[0, :, 0, K // 2 - 1, K // 2 - 1] = 1.0
+    volts = e[:, None, :, None].astype(np.complex128)
+    return volts, kern, ant_xy, f, n, cells, s, (qs, ps)
+
+
+def test_point_source_closed_form():
+    volts, kern, ant_xy, f, n, cells, s, (qs, ps) = _lone_source_delta()
+    img = ora.image(volts, kern, ant_xy, [f], [n], 1.0)[0][0].real
+    A = cells.shape[0]
+    pw = np.sum(np.abs(s) ** 2)
+    assert np.unravel_index(np.argmax(img), img.shape) == (qs, ps)
+    assert abs(img[qs, ps] - A * A * pw) < 1e-9 * A * A * pw
+    # everywhere: the array PSF centred on the source, sum_t|s|^2 |sum_a w^{r_a.(q - q_s)}|^2
+    q = np.arange(n)
+    phase = (cells[:, 0][:, None, None] * (q[None, :, None] - qs) +
+             cells[:, 1][:, None, None] * (q[None, None, :] - ps)) / n
+    psf = np.abs(np.exp(2j * np.pi * phase).sum(axis=0)) ** 2 * pw
+    assert np.abs(img - psf).max() < 1e-9 * A * A * pw
+
+
+@pytest.mark.parametrize("dq", [(5, -3), (-7, 2), (0, 6)])
+def test_point_source_gaussian_kernels(dq):
+    """Generator kernels (sigma 1 cell Gaussians with random gains): the peak lands on the source pixel."""
+    cfg = configs.scaled(configs.TINY, n_ant=64, n_time=16, n_src=1)
+    geo = synth.geometry(cfg)
+    g = synth.gains(cfg)
+    kern = synth.kernels(geo, g, 1)
+    n = cfg.grid_n
+    qs, ps = n // 2 + dq[0], n // 2 + dq[1]
+    sk = synth.Sky(np.array([2.0]), np.array([[(ps - n / 2) / n, (qs - n / 2) / n]]))
+    lam = geo.freqs_hz[0] / configs.C_LIGHT
+    rng = np.random.default_rng(0)
+    s = rng.standard_normal(cfg.n_time) + 1j * rng.standard_normal(cfg.n_time)
+    ph = np.exp(-2j * np.pi * lam * (geo.ant_xy_m[:, 0] * sk.lm[0, 0] + geo.ant_xy_m[:, 1] * sk.lm[0, 1]))
+    e = s[:, None] * np.conj(g[:, 0])[None, :] * ph[None, :]
+    img = ora.image(e[:, None, :, None], kern, geo.ant_xy_m, geo.freqs_hz, geo.grid_n, 1.0)[0][0].real
+    assert np.unravel_index(np.argmax(img), img.shape) == (qs, ps)
+
+
+def test_point_source_mirrored_sign_fails():
+    """The e^{-2 pi i} transform (the paper's F^T read literally) would put the source at -(l, m)."""
+    volts, kern, ant_xy, f, n, cells, s, (qs, ps) = _lone_source_delta(dq=(4, 6))
+    img = ora.image(volts, kern, ant_xy, [f], [n], 1.0)[0][0].real
+    assert img[qs, ps] > 10 * img[n - qs, n - ps]
+
+
+# ---------------------------------------------------------------------------------------------------------
+# 4. Reduction to the direct-imaging correlator and numpy's inverse FFT
+# ---------------------------------------------------------------------------------------------------------
+def test_delta_kernels_reduce_to_ifft2():
+    rng = np.random.default_rng(11)
+    n, A, T, K = 32, 16, 5, 4
+    cells = np.stack([rng.integers(4, n - 4, A), rng.integers(4, n - 4, A)], axis=1)
+    ant_xy = np.stack([cells[:, 1] - n / 2 + 0.25, cells[:, 0] - n / 2 + 0.75], axis=1)   # sub-cell offsets
+    e = rng.standard_normal((T, A)) + 1j * rng.standard_normal((T, A))
+    kern = np.zeros((1, A, 1, K, K), dtype=np.complex64)
+    kern[0, :, 0, K // 2 - 1, K // 2 - 1] = 1.0
+    img = ora.image(e[:, None, :, None], kern, ant_xy, [configs.C_LIGHT], [n], 1.0)[0][0]
+    ref = direct_imaging(e, cells, n)
+    assert _peak_err(img, ref) < 1e-12
+
+
+# ---------------------------------------------------------------------------------------------------------
+# 5. Single antenna: its power beam; centre pixel |sum_k K(k)|^2 sum_t |E_t|^2
+# ---------------------------------------------------------------------------------------------------------
+def test_single_antenna_beam():
+    rng = np.random.default_rng(5)
+    n, K, T = 32, 4, 7
+    ant_xy = np.array([[1.3, -2.6]])
+    kern = (rng.standard_normal((1, 1, 1, K, K)) + 1j * rng.standard_normal((1, 1, 1, K, K))).astype(np.complex64)
+    e = rng.standard_normal((T, 1)) + 1j * rng.standard_normal((T, 1))
+    img = ora.image(e[:, None, :, None], kern, ant_xy, [configs.C_LIGHT], [n], 1.0)[0][0]
+    pw = np.sum(np.abs(e) ** 2)
+    k128 = kern[0, 0, 0].astype(np.complex128)
+    assert abs(img[n // 2, n // 2] - pw * abs(k128.sum()) ** 2) < 1e-10 * pw * abs(k128.sum()) ** 2
+    # whole image = |2-D DTFT of the kernel|^2 * power (shift-invariant, so the footprint origin drops out)
+    ft = np.fft.fftshift(np.fft.ifft2(np.pad(k128, ((0, n - K), (0, n - K))))) * n * n
+    assert _peak_err(img, pw * np.abs(ft) ** 2) < 1e-12
+
+
+# ---------------------------------------------------------------------------------------------------------
+# 6. Invariants
+# ---------------------------------------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def dual():
+    cfg, geo, kern, volts = _small(2, A=20, n=32, T=6, seed=9)
+    img = ora.image(volts, kern, geo.ant_xy_m, geo.freqs_hz, geo.grid_n, cfg.cell_lambda)[0]
+    return cfg, geo, kern, volts, img
+
+
+def test_invariant_integer_shift(dual):
+    cfg, geo, kern, volts, img = dual
+    shifted = geo.ant_xy_m + np.array([3.0, -2.0]) * configs.C_LIGHT / geo.freqs_hz[0] * cfg.cell_lambda
+    img2 = ora.image(volts, kern, shifted, geo.freqs_hz, geo.grid_n, cfg.cell_lambda)[0]
+    for k in range(4):
+        assert _peak_err(img2[k], img[k]) < 1e-11
+
+
+def test_invariant_scale(dual):
+    cfg, geo, kern, volts, img = dual
+    e = ora.unpack(volts) * (0.5 - 2.0j)
+    img2 = ora.image(e, kern, geo.ant_xy_m, geo.freqs_hz, geo.grid_n, cfg.cell_lambda)[0]
+    assert _peak_err(img2, img * abs(0.5 - 2.0j) ** 2) < 1e-12
+
+
+def test_invariant_pol_swap(dual):
+    cfg, geo, kern, volts, img = dual
+    img2 = ora.image(volts[:, :, :, ::-1], kern[:, :, ::-1], geo.ant_xy_m, geo.freqs_hz, geo.grid_n,
+                     cfg.cell_lambda)[0]
+    for a, b in [(0, 1), (1, 0), (2, 3), (3, 2)]:
+        assert _peak_err(img2[a], img[b]) < 1e-12
+
+
+def test_invariant_hermitian_and_cauchy_schwarz(dual):
+    img = dual[4]
+    assert _peak_err(img[3], np.conj(img[2])) < 1e-13
+    assert np.abs(img[0].imag).max() < 1e-12 * np.abs(img[0]).max()
+    assert img[0].real.min() >= 0 and img[1].real.min() >= 0
+    assert np.all(np.abs(img[2]) ** 2 <= img[0].real * img[1].real * (1 + 1e-9) + 1e-9)
+
+
+def test_invariant_conjugate_mirrors(dual):
+    cfg, geo, kern, volts, img = dual
+    n = cfg.grid_n
+    e = np.conj(ora.unpack(volts))
+    img2 = ora.image(e, np.conj(kern), geo.ant_xy_m, geo.freqs_hz, geo.grid_n, cfg.cell_lambda)[0]
+    mirror = (n - np.arange(n)) % n
+    for a, b in [(0, 0), (1, 1), (2, 3), (3, 2)]:
+        assert _peak_err(img2[a], img[b][np.ix_(mirror, mirror)]) < 1e-12
+
+
+def test_footprint_outside_grid_rejected():
+    with pytest.raises(ValueError):
+        ora.footprint_origin(np.array([[40.0, 0.0]]), configs.C_LIGHT, 1.0, 64, 4)
+
+
+def test_pixel_route_matches_full_image(dual):
+    cfg, geo, kern, volts, img = dual
+    pix = np.array([[0, 0], [16, 16], [3, 29], [31, 7]])
+    got = ora.image_pixels(volts, kern[0], geo.ant_xy_m, geo.freqs_hz[0], cfg.grid_n, cfg.cell_lambda, pix,
+                           t_batch=4)
+    for k in range(4):
+        ref = img[k][pix[:, 0], pix[:, 1]]
+        assert np.abs(got[k] - ref).max() < 1e-11 * np.abs(img[k]).max()
