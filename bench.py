@@ -1,0 +1,185 @@
+"""Benchmark of the MOFF hot path on one MI355X: channel-samples imaged per second.
+
+Workload (the headline configuration): 2048 antennas in a 200-wavelength disk (at 130 MHz), 128 channels over
+100-130 MHz, dual polarisation (XX, YY, XY, YX), 4x4 kernels, 256^2 grid, 16384 time samples of int8
+voltages, synthetic and seeded (``paper_0812_3669_amd.synth``).  One step = the whole hot path over the whole
+integration: zero the accumulator, grid + 2-D FFT + products for all 128 x 16384 channel-samples
+(moff_correlate), and the read-out of the 128 images (moff_read_image).  Voltages (17.2 GB) and kernels are
+resident in HBM before the timed region starts.
+
+Prints one JSON line.  ``--gpus N`` with N > 1 exits: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_VECTOR = 157.3e12    # MI355X published FP32 vector peak (packed FP32), FLOP/s
+PEAK_HBM = 8.0e12              # MI355X HBM3E, B/s
+
+
+def _src_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_0812_3669_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic(kernel: str, launches_cs: float):
+    """HBM bytes per launch of ``kernel`` from the committed rocprofv3 PMC summary, if it was taken on the
+    current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    if d.get("src_hash") != _src_hash() or kernel not in d.get("kernels", {}):
+        return None
+    return d["kernels"][kernel].get("bytes_per_launch")
+
+
+def cpu_baseline(cfg, geo, kern_np, volts_dev, budget_s: float = 12.0):
+    """The FP64 oracle timed on this host on a bounded sample: channel 0, growing sample counts."""
+    import numpy as np
+    try:
+        from threadpoolctl import threadpool_limits
+    except Exception:  # pragma: no cover
+        threadpool_limits = None
+    from oracle import moff_oracle as ora
+    cores = len(os.sched_getaffinity(0))
+    ctx = threadpool_limits(limits=cores) if threadpool_limits else None
+    try:
+        n_done, t_used, t = 0, 0.0, 4
+        sel = [0]
+        while t_used < budget_s and t <= cfg.n_time:
+            v = volts_dev[:t, 0:1].cpu().numpy()
+            t0 = time.perf_counter()
+            ora.image(v, kern_np[sel], geo.ant_xy_m, geo.freqs_hz[sel], geo.grid_n[sel], cfg.cell_lambda)
+            dt = time.perf_counter() - t0
+            n_done, t_used = t, dt
+            t *= 2
+    finally:
+        if ctx is not None:
+            ctx.__exit__(None, None, None)
+    return {"value": n_done / t_used, "unit": "channel-samples/s", "cores": cores, "kind": "oracle",
+            "sample": f"FP64 oracle (direct DFT) on channel 0 x {n_done} samples of the same workload, "
+                      f"{t_used:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--acc", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--time", type=int, default=0, help="samples per step (default: the full 16384)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true", help="run a 1 GiB device copy (PMC calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs the MOFF hot path on one GPU only (asked for --gpus {args.gpus}); "
+              "multi-GPU sharding is a design note, not part of this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_0812_3669_amd import api, configs, synth
+
+    dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        a = torch.ones(1 << 28, dtype=torch.float32, device=dev)       # 1 GiB
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": a.numel() * 4, "launches": 3}))
+        return
+
+    cfg = configs.HEADLINE
+    T = args.time or cfg.n_time
+    print(f"bench: building workload {cfg.name} (T={T})", file=sys.stderr, flush=True)
+    geo = synth.geometry(cfg)
+    g = synth.gains(cfg)
+    sk = synth.sky(cfg)
+    kern_np = synth.kernels(geo, g, cfg.n_pol)
+    volts = synth.DeviceVoltages(cfg, geo, g, sk, dev, chunk=64).all(T)
+    acc_mode = api.ACC_FP64_COMP if args.acc == "fp64" else api.ACC_FP32
+    plan = api.plan_for(cfg, geo, acc_mode=acc_mode).bind(dev)
+    plan.set_kernels(torch.from_numpy(kern_np).to(dev))
+    acc = plan.new_accumulator()
+    torch.cuda.synchronize()
+    print("bench: workload resident; warmup", file=sys.stderr, flush=True)
+
+    def step():
+        acc.zero_()
+        plan.correlate(volts, acc, n_t=T)
+        return plan.read_image(acc, n_samples=T, split=False)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    plan.profile(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        img = step()
+    e1.record()
+    torch.cuda.synchronize()
+    plan.profile(False)
+    ms = e0.elapsed_time(e1) / args.steps
+    cs = cfg.n_chan * T
+    value = cs / (ms / 1e3)
+    print(f"bench: {ms:.2f} ms/step", file=sys.stderr, flush=True)
+
+    # per-kernel event timing over the timed steps
+    n, P, K, A = 256, cfg.n_pol, cfg.ksize, cfg.n_ant
+    flops = {0: 8.0 * A * P * K * K + 5.0 * n * n * math.log2(n) * P,        # gridding + row FFTs
+             1: 5.0 * n * n * math.log2(n) * P + 16.0 * n * n}             # column FFTs + products
+    names = {0: "k_rows", 1: "k_cols"}
+    kt = {}
+    for kind in (0, 1):
+        tot_ms, launches, kcs = plan.profile_read(kind)
+        kt[kind] = dict(ms=tot_ms, launches=launches, cs=kcs)
+    dom = max(kt, key=lambda k: kt[k]["ms"])
+    d = kt[dom]
+    avg_ms = d["ms"] / max(d["launches"], 1)
+    per_launch_flops = flops[dom] * d["cs"] / max(d["launches"], 1)
+    achieved = per_launch_flops / (avg_ms / 1e3)
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP32_VECTOR, "traffic": _traffic(names[dom], None),
+                "kernel": names[dom], "avg_launch_ms": avg_ms,
+                "kernel_share": {names[k]: kt[k]["ms"] / (kt[0]["ms"] + kt[1]["ms"]) for k in kt}}
+
+    out = {
+        "metric": "channel-samples imaged/s (N=2048, 256^2 grid), plain FP32 path",
+        "value": value, "unit": "channel-samples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded point sources + noise, int8 voltages)",
+        "config": {"workload": "headline: 2048 antennas, 200-lambda disk, 128 channels 100-130 MHz, 2 pols, "
+                               "4x4 kernels, 256^2 grid, 16384 samples, int8",
+                   "channel_samples_per_step": cs, "accumulator": args.acc,
+                   "algorithmic_flops_per_cs": cfg.flops_per_cs(),
+                   "achieved_algorithmic_tflops": value * cfg.flops_per_cs() / 1e12},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, geo, kern_np, volts)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

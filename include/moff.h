@@ -1,0 +1,153 @@
+/* moff.h -- C ABI of the MI355X-native MOFF correlator hot path.
+ *
+ * The MOFF image (Section 4, Eq. m6) is
+ *
+ *     I'(theta) = < | F^T(theta, r) W^T(r, a) N~(a, a) E'(a) |^2 >_t
+ *
+ * computed for every frequency channel c and time sample t as
+ *   1. noise weighting N~ (diagonal, folded into the kernels by the caller),
+ *   2. gridding W^T: each antenna's channelised voltage E'_a is spread onto a regular n x n grid through its own
+ *      K x K complex kernel (multiplied as given, no conjugation),
+ *   3. the spatial transform F^T: an unnormalised 2-D DFT with the e^{+2 pi i} sign (the adjoint of the
+ *      e^{-2 pi i u.theta} of the voltage model, Eq. Ea), evaluated as an FFT (Fig. 1 caption, rows d-e),
+ *   4. squaring into polarisation products XX = |E_X|^2, YY = |E_Y|^2, XY = E_X conj(E_Y), summed over time
+ *      (YX = conj(XY) pixel by pixel; Discussion: four polarisations).
+ *
+ * Geometry conventions (Section 4, MOFF properties 1-2: arbitrary antenna placement, free grid spacing; the
+ * grid is tied to the ground, east = u = column i, north = v = row j):
+ *   X_a = x_a f_c / c / cell + n_c / 2,  Y_a likewise from y_a;
+ *   the footprint of antenna a covers columns floor(X_a) - K/2 + 1 ... floor(X_a) + K/2 (rows likewise) and must
+ *   lie inside the grid (otherwise MOFF_E_INVALID);
+ *   image pixel (q, p) <-> direction (m, l) = ((q - n/2), (p - n/2)) / (n cell).
+ *
+ * Memory and streams.  Every device buffer is caller-owned (the library never allocates device memory).  Every
+ * call that takes a stream only enqueues work on it and returns without synchronising; a stream argument is a
+ * hipStream_t passed as void* (NULL = the null stream).  Validation is done on the host before anything is
+ * enqueued: on error nothing is enqueued and outputs are untouched.  Asynchronous device faults surface at the
+ * caller's next synchronisation.  A plan is used by one host thread at a time; distinct plans may run
+ * concurrently on distinct streams.  Results are deterministic for identical inputs.
+ *
+ * Layouts (all little-endian, densely packed):
+ *   voltages    int8  [n_t][C][A][P][2] (re, im)            (volt_format MOFF_VOLT_INT8)
+ *               float [n_t][C][A][P][2] (complex64)          (volt_format MOFF_VOLT_C64)
+ *   kernels     float [C][A][P][K][K][2] (complex64), the weight N~ already folded in
+ *   grid/efield float [n_t][sum_c P n_c^2][2]: per sample, channel c's block starts at P * pix_off(c), pol p at
+ *               + p n_c^2, row-major [j][i].  E-field images are in FFT order: index k <-> pixel (k + n/2) mod n.
+ *   accumulator float (MOFF_ACC_FP32) or double pairs (sum, carry) (MOFF_ACC_FP64_COMP) [sum_c R n_c^2], with R = 4
+ *               reals per pixel (XX, YY, Re XY, Im XY) for P = 2 and R = 1 for P = 1, channel c at R * pix_off(c),
+ *               pixels in FFT order.  Zero it before the first call (any fill kernel); calls add to it.
+ *   image       float [sum_c M n_c^2][2] (complex64), M = 4 products XX, YY, XY, YX (M = 1 for P = 1), channel c at
+ *               M * pix_off(c), product-major, pixels centred (row q = m, column p = l).
+ *   pix_off(c) = sum_{c' < c} n_c'^2  (moff_chan_offset).
+ */
+#ifndef MOFF_H
+#define MOFF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct moff_plan_s *moff_plan_t;
+
+typedef enum {
+  MOFF_OK = 0,
+  MOFF_E_INVALID = 1,     /* bad argument: null pointer, odd K, footprint outside the grid, bad size */
+  MOFF_E_BUDGET = 2,      /* workspace smaller than moff_workspace_size */
+  MOFF_E_DEVICE = 3,      /* a HIP call or kernel launch failed */
+  MOFF_E_UNSUPPORTED = 4, /* valid request this build does not implement (e.g. a grid size with a prime > 5) */
+  MOFF_E_STATE = 5        /* call out of order: not bound, kernels not set */
+} moff_status;
+
+typedef enum { MOFF_FFT_FP32 = 0, MOFF_FFT_SPLIT_FP16 = 1, MOFF_FFT_SPLIT_BF16 = 2 } moff_fft_mode;
+typedef enum { MOFF_ACC_FP32 = 0, MOFF_ACC_FP64_COMP = 1 } moff_acc_mode;
+typedef enum { MOFF_VOLT_INT8 = 0, MOFF_VOLT_C64 = 1 } moff_volt_format;
+
+typedef struct {
+  int32_t n_ant;            /* A >= 1 */
+  int32_t n_pol;            /* P = 1 or 2 */
+  int32_t n_chan;           /* C >= 1 */
+  int32_t ksize;            /* K, even, 2..8 */
+  const double *ant_xy_m;   /* host [A][2] (east, north) metres; copied by moff_plan */
+  const double *freq_hz;    /* host [C] channel centre frequencies; copied */
+  const int32_t *grid_n;    /* host [C] grid sizes, or NULL / 0 entries = smallest supported size that fits */
+  double cell_lambda;       /* grid cell size in wavelengths (> 0) */
+  int32_t fft_mode;         /* moff_fft_mode */
+  int32_t acc_mode;         /* moff_acc_mode */
+  int32_t time_block;       /* samples per fused launch block (0 = library default) */
+  int32_t volt_format;      /* moff_volt_format */
+} moff_plan_desc;
+
+/* Host only.  Validates the description, computes every antenna's footprint per channel, bins antennas into
+ * grid row bands (an antenna whose footprint straddles a band boundary is listed in both bands: the paper's
+ * module-boundary copies, Section 5) and lays out the workspace.  *out receives a new plan. */
+moff_status moff_plan(const moff_plan_desc *desc, moff_plan_t *out);
+
+/* Bytes of device workspace the plan needs (>= 256-byte aligned sections). */
+moff_status moff_workspace_size(moff_plan_t plan, size_t *bytes);
+
+/* Bytes of the accumulator buffer (depends on acc_mode) and of the image buffer, for all channels. */
+moff_status moff_acc_size(moff_plan_t plan, size_t *bytes);
+moff_status moff_image_size(moff_plan_t plan, size_t *bytes);
+
+/* Grid size chosen for channel chan, and pix_off(chan) = sum of n_c^2 over earlier channels. */
+moff_status moff_grid_n(moff_plan_t plan, int32_t chan, int32_t *n);
+moff_status moff_chan_offset(moff_plan_t plan, int32_t chan, int64_t *pix_off);
+
+/* Binds device workspace d_ws (>= moff_workspace_size bytes, 256-byte aligned) to the plan: uploads the band
+ * lists and tap tables and generates the FFT twiddle tables on the device in FP64 (rounded once to FP32).
+ * The workspace must stay allocated while the plan is used. */
+moff_status moff_bind(moff_plan_t plan, void *d_ws, size_t bytes, void *stream);
+
+/* Sets the per-antenna kernels (layout above, device memory).  Re-orders them into the library's tap-group
+ * order inside the workspace; d_kern may be freed once the stream has passed this call.  Step 1-2 of Eq. m6:
+ * the caller folds N~ into the kernels. */
+moff_status moff_set_kernels(moff_plan_t plan, const void *d_kern, void *stream);
+
+/* Staged path, step 2 (gridding): d_volt [n_t] samples -> d_grid [n_t] grids (layout above, fully written). */
+moff_status moff_grid(moff_plan_t plan, const void *d_volt, int64_t n_t, void *d_grid, void *stream);
+
+/* Staged path, step 3: in-place 2-D FFT of n_t grids into E-field images (FFT pixel order). */
+moff_status moff_fft(moff_plan_t plan, void *d_grid, int64_t n_t, void *stream);
+
+/* Staged path, step 4: adds the polarisation products of n_t E-field images to the accumulator. */
+moff_status moff_accumulate(moff_plan_t plan, const void *d_efield, int64_t n_t, void *d_acc, void *stream);
+
+/* Fused path: steps 1-4 for n_t samples of all channels, added to the accumulator.  Uses only the workspace
+ * as scratch (the row-transformed grids pass through it between the row and column passes). */
+moff_status moff_correlate(moff_plan_t plan, const void *d_volt, int64_t n_t, void *d_acc, void *stream);
+
+/* Read-out: accumulator -> centred complex64 image (layout above), expanding YX = conj(XY).  normalize != 0
+ * divides by n_samples (the time average of Eq. m6); otherwise the sums are returned. */
+moff_status moff_read_image(moff_plan_t plan, const void *d_acc, int64_t n_samples, int32_t normalize,
+                            void *d_img, void *stream);
+
+/* Test hooks.  moff_debug_unpack converts one sample's voltages ([C][A][P][2]) exactly to float [C][A][P][2].
+ * moff_debug_tiles copies (host to host) the footprint origins int32 [C][A][2] (j0, i0), the band pointer array
+ * int32 [n_band_total + 1] and the band antenna list int32 [n_entries]; any pointer may be NULL, and
+ * moff_debug_tile_counts gives the sizes and the band height per channel (int32 [C], may be NULL). */
+moff_status moff_debug_unpack(moff_plan_t plan, const void *d_volt, float *d_out, void *stream);
+moff_status moff_debug_tile_counts(moff_plan_t plan, int64_t *n_band_total, int64_t *n_entries,
+                                   int32_t *band_rows);
+moff_status moff_debug_tiles(moff_plan_t plan, int32_t *h_origin, int32_t *h_band_ptr, int32_t *h_band_ant);
+
+/* Kernel timing (tracing).  moff_profile(plan, 1) starts recording a pair of HIP events around every launch of
+ * the fused path on the caller's stream (earlier records are dropped); moff_profile(plan, 0) stops.  After the
+ * stream has been synchronised, moff_profile_read sums, for kernel kind 0 (row pass: gridding + row FFTs) or
+ * 1 (column pass: column FFTs + products + accumulation), the event-measured time in ms, the launch count and
+ * the channel-samples those launches processed.  Recording adds two event records per launch. */
+moff_status moff_profile(moff_plan_t plan, int32_t enable);
+moff_status moff_profile_read(moff_plan_t plan, int32_t kind, double *total_ms, int64_t *launches,
+                              int64_t *channel_samples);
+
+void moff_plan_destroy(moff_plan_t plan);
+const char *moff_status_str(moff_status s);
+/* Text of the most recent error on this thread ("" if none). */
+const char *moff_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MOFF_H */

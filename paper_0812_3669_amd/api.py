@@ -1,0 +1,230 @@
+"""Python binding of the MOFF hot path: torch for device memory and streams, every step in ``libmoff.so``.
+
+    plan = Plan(ant_xy_m, freqs_hz, grid_n, n_pol=2, ksize=4)        # host-only plan
+    plan.bind()                                                       # device workspace + twiddles
+    plan.set_kernels(kern)                                            # complex64 [C, A, P, K, K] on the GPU
+    acc = plan.new_accumulator()
+    plan.correlate(volts, acc)                                        # int8 [T, C, A, P, 2] on the GPU
+    images = plan.read_image(acc, n_samples=T)                        # list of complex64 [M, n, n]
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+from . import _lib
+from ._lib import ACC_FP32, ACC_FP64_COMP, FFT_FP32, VOLT_C64, VOLT_INT8  # noqa: F401
+
+
+class MoffError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        self.status = status
+        lib = _lib.load()
+        name = lib.moff_status_str(status).decode()
+        super().__init__(f"{where}: {name}: {msg}")
+
+
+def _check(status: int, where: str):
+    if status != 0:
+        lib = _lib.load()
+        raise MoffError(status, where, lib.moff_last_error().decode())
+
+
+def _stream_handle(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t) -> C.c_void_p:
+    return C.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """A MOFF correlation plan (geometry, band binning, workspace) for one array and channel set."""
+
+    def __init__(self, ant_xy_m, freqs_hz, grid_n=None, n_pol: int = 2, ksize: int = 4, cell_lambda: float = 1.0,
+                 fft_mode: int = FFT_FP32, acc_mode: int = ACC_FP32, time_block: int = 0,
+                 volt_format: int = VOLT_INT8):
+        self.lib = _lib.load()
+        xy = np.ascontiguousarray(ant_xy_m, dtype=np.float64)
+        fr = np.ascontiguousarray(freqs_hz, dtype=np.float64)
+        self.n_ant, self.n_chan, self.n_pol, self.ksize = xy.shape[0], fr.shape[0], n_pol, ksize
+        self.acc_mode, self.volt_format = acc_mode, volt_format
+        gn = None
+        if grid_n is not None:
+            gn = np.ascontiguousarray(np.broadcast_to(np.asarray(grid_n, dtype=np.int32), (self.n_chan,)))
+        d = _lib.PlanDesc()
+        d.n_ant, d.n_pol, d.n_chan, d.ksize = self.n_ant, n_pol, self.n_chan, ksize
+        d.ant_xy_m = xy.ctypes.data_as(C.POINTER(C.c_double))
+        d.freq_hz = fr.ctypes.data_as(C.POINTER(C.c_double))
+        d.grid_n = gn.ctypes.data_as(C.POINTER(C.c_int32)) if gn is not None else None
+        d.cell_lambda = cell_lambda
+        d.fft_mode, d.acc_mode, d.time_block, d.volt_format = fft_mode, acc_mode, time_block, volt_format
+        h = C.c_void_p()
+        _check(self.lib.moff_plan(C.byref(d), C.byref(h)), "moff_plan")
+        self._h = h
+        self._ws = None
+        self._kern_ref = None
+        self.grid_n = []
+        self.pix_off = []
+        for c in range(self.n_chan):
+            n = C.c_int32()
+            o = C.c_int64()
+            _check(self.lib.moff_grid_n(h, c, C.byref(n)), "moff_grid_n")
+            _check(self.lib.moff_chan_offset(h, c, C.byref(o)), "moff_chan_offset")
+            self.grid_n.append(n.value)
+            self.pix_off.append(o.value)
+        self.pix_total = self.pix_off[-1] + self.grid_n[-1] ** 2
+        self.n_prod = 4 if n_pol == 2 else 1
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self.lib.moff_plan_destroy(h)
+            self._h = None
+
+    # ---- sizes -------------------------------------------------------------------------------------------------
+    def _size(self, fn) -> int:
+        b = C.c_size_t()
+        _check(fn(self._h, C.byref(b)), fn.__name__)
+        return b.value
+
+    @property
+    def workspace_bytes(self) -> int:
+        return self._size(self.lib.moff_workspace_size)
+
+    @property
+    def acc_bytes(self) -> int:
+        return self._size(self.lib.moff_acc_size)
+
+    @property
+    def image_bytes(self) -> int:
+        return self._size(self.lib.moff_image_size)
+
+    # ---- device state --------------------------------------------------------------------------------------------
+    def bind(self, device="cuda", stream=None):
+        import torch
+        n = max(self.workspace_bytes, 256)
+        self._ws = torch.empty(n + 256, dtype=torch.uint8, device=device)
+        base = self._ws.data_ptr()
+        aligned = (base + 255) & ~255
+        _check(self.lib.moff_bind(self._h, C.c_void_p(aligned), C.c_size_t(n), _stream_handle(stream)),
+               "moff_bind")
+        self.device = self._ws.device
+        return self
+
+    def set_kernels(self, kern, stream=None):
+        """kern: complex64 [C, A, P, K, K] on the device (the noise weight folded in)."""
+        import torch
+        assert kern.dtype == torch.complex64 and kern.is_contiguous()
+        assert tuple(kern.shape) == (self.n_chan, self.n_ant, self.n_pol, self.ksize, self.ksize), kern.shape
+        _check(self.lib.moff_set_kernels(self._h, _ptr(kern), _stream_handle(stream)), "moff_set_kernels")
+        self._kern_ref = kern   # keep alive until the packing kernel has run
+        return self
+
+    def new_accumulator(self):
+        import torch
+        dt = torch.float64 if self.acc_mode == ACC_FP64_COMP else torch.float32
+        elems = self.acc_bytes // (8 if dt == torch.float64 else 4)
+        return torch.zeros(elems, dtype=dt, device=self.device)
+
+    def _check_volts(self, volts, n_t):
+        import torch
+        if self.volt_format == VOLT_INT8:
+            assert volts.dtype == torch.int8 and volts.shape[-1] == 2
+            per = self.n_chan * self.n_ant * self.n_pol * 2
+        else:
+            assert volts.dtype == torch.complex64
+            per = self.n_chan * self.n_ant * self.n_pol
+        assert volts.is_contiguous() and volts.numel() >= n_t * per, (volts.shape, n_t)
+
+    # ---- the hot path ---------------------------------------------------------------------------------------------
+    def correlate(self, volts, acc, n_t: Optional[int] = None, stream=None):
+        n_t = volts.shape[0] if n_t is None else n_t
+        self._check_volts(volts, n_t)
+        _check(self.lib.moff_correlate(self._h, _ptr(volts), n_t, _ptr(acc), _stream_handle(stream)),
+               "moff_correlate")
+
+    def grid(self, volts, n_t: Optional[int] = None, out=None, stream=None):
+        import torch
+        n_t = volts.shape[0] if n_t is None else n_t
+        self._check_volts(volts, n_t)
+        if out is None:
+            out = torch.empty(n_t * self.n_pol * self.pix_total, dtype=torch.complex64, device=self.device)
+        _check(self.lib.moff_grid(self._h, _ptr(volts), n_t, _ptr(out), _stream_handle(stream)), "moff_grid")
+        return out
+
+    def fft(self, grid, n_t: int, stream=None):
+        _check(self.lib.moff_fft(self._h, _ptr(grid), n_t, _stream_handle(stream)), "moff_fft")
+        return grid
+
+    def accumulate(self, efield, n_t: int, acc, stream=None):
+        _check(self.lib.moff_accumulate(self._h, _ptr(efield), n_t, _ptr(acc), _stream_handle(stream)),
+               "moff_accumulate")
+
+    def read_image(self, acc, n_samples: int = 0, normalize: bool = False, stream=None, split: bool = True):
+        import torch
+        img = torch.empty(self.n_prod * self.pix_total, dtype=torch.complex64, device=self.device)
+        _check(self.lib.moff_read_image(self._h, _ptr(acc), n_samples, int(bool(normalize)), _ptr(img),
+                                        _stream_handle(stream)), "moff_read_image")
+        if not split:
+            return img
+        return self.split_images(img)
+
+    def split_images(self, flat) -> List:
+        out = []
+        for c in range(self.n_chan):
+            n = self.grid_n[c]
+            o = self.n_prod * self.pix_off[c]
+            out.append(flat[o:o + self.n_prod * n * n].view(self.n_prod, n, n))
+        return out
+
+    def split_grids(self, flat, n_t: int) -> List:
+        """Staged grid/E-field buffer -> list over channels of [n_t, P, n, n] views."""
+        per = self.n_pol * self.pix_total
+        v = flat[: n_t * per].view(n_t, per)
+        out = []
+        for c in range(self.n_chan):
+            n = self.grid_n[c]
+            o = self.n_pol * self.pix_off[c]
+            out.append(v[:, o:o + self.n_pol * n * n].view(n_t, self.n_pol, n, n))
+        return out
+
+    # ---- kernel timing ------------------------------------------------------------------------------------------------
+    def profile(self, enable: bool):
+        _check(self.lib.moff_profile(self._h, int(bool(enable))), "moff_profile")
+
+    def profile_read(self, kind: int):
+        """(total ms, launches, channel-samples) of kind 0 (row pass) or 1 (column pass); syncs the events."""
+        ms, n, cs = C.c_double(), C.c_int64(), C.c_int64()
+        _check(self.lib.moff_profile_read(self._h, kind, C.byref(ms), C.byref(n), C.byref(cs)), "moff_profile_read")
+        return ms.value, n.value, cs.value
+
+    # ---- test hooks ------------------------------------------------------------------------------------------------
+    def debug_unpack(self, volt_sample, stream=None):
+        import torch
+        out = torch.empty(self.n_chan * self.n_ant * self.n_pol * 2, dtype=torch.float32, device=self.device)
+        _check(self.lib.moff_debug_unpack(self._h, _ptr(volt_sample), _ptr(out), _stream_handle(stream)),
+               "moff_debug_unpack")
+        return out.view(self.n_chan, self.n_ant, self.n_pol, 2)
+
+    def debug_tiles(self):
+        nb, ne = C.c_int64(), C.c_int64()
+        rows = np.zeros(self.n_chan, dtype=np.int32)
+        _check(self.lib.moff_debug_tile_counts(self._h, C.byref(nb), C.byref(ne),
+                                               rows.ctypes.data_as(C.POINTER(C.c_int32))), "tile counts")
+        origin = np.zeros((self.n_chan, self.n_ant, 2), dtype=np.int32)
+        ptr = np.zeros(nb.value + 1, dtype=np.int32)
+        ant = np.zeros(max(ne.value, 1), dtype=np.int32)
+        ip = lambda a: a.ctypes.data_as(C.POINTER(C.c_int32))  # noqa: E731
+        _check(self.lib.moff_debug_tiles(self._h, ip(origin), ip(ptr), ip(ant)), "moff_debug_tiles")
+        return origin, ptr, ant[: ne.value], rows
+
+
+def plan_for(cfg, geo, **kw) -> "Plan":
+    """Plan for a workload description (``configs.Config``) and its geometry (``synth.Geometry``)."""
+    return Plan(geo.ant_xy_m, geo.freqs_hz, geo.grid_n, n_pol=cfg.n_pol, ksize=cfg.ksize,
+                cell_lambda=cfg.cell_lambda, volt_format=VOLT_INT8 if cfg.int8 else VOLT_C64, **kw)

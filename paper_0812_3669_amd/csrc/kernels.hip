@@ -1,0 +1,721 @@
+// HIP kernels of the MOFF hot path for CDNA4 (gfx950), plain FP32 form.
+//
+// Eq. m6 per channel c and sample t:  grid (step 2) -> 2-D FFT (step 3) -> |.|^2 products summed over t.
+//
+// Fused path, per launch block (channels of one grid size x a block of samples):
+//   k_rows<FUSED>: one workgroup per (row band, time group).  The band's row range of the channel's grid is
+//     built in LDS from the int8 voltages (the channel's voltage row is staged in LDS with coalesced loads)
+//     by a deterministic scatter: wavefront w owns the band rows r with (r - row0) % 4 == w and processes the
+//     plan's tap groups, 64 taps on 64 distinct cells per instruction, so the sums need no atomics and their
+//     order is fixed.  The rows are then transformed (Stockham radix stages, butterflies in registers, LDS
+//     exchanges) and written to the block's row-transform buffer H.  Rows no footprint touches are skipped.
+//   k_cols<FUSED>: one workgroup per (channel, group of W columns) for all samples of the block: column FFTs
+//     (first stage straight from H, reading only rows some footprint touched), then XX, YY, XY products in
+//     registers, summed over the block in FP32 and added once to the accumulator (FP32 or FP64 sum + carry).
+//   The exchange between the two passes is the row-d inter-module traffic of Fig. 1: a 2-D FFT of a grid larger
+//   than one CU's LDS needs one all-to-all, and here it goes through L2/MALL/HBM between two kernels.
+// Staged path: k_grid (gridding only), k_rows<ROWFFT> + k_cols<COLFFT> (in-place 2-D FFT), k_acc_staged.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <mutex>
+#include <set>
+#include <utility>
+
+#include "fft_radix.h"
+#include "kernels.h"
+
+namespace moff {
+
+// ------------------------------------------------------------------------------------------------------------
+// Utility kernels
+// ------------------------------------------------------------------------------------------------------------
+
+// Twiddle table tw[e] = exp(+2 pi i e / n), generated in FP64 from the exact rational angle and rounded once.
+__global__ void k_twiddle_f64(float2 *tw, int n) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  double s, c;
+  sincospi(2.0 * (double)e / (double)n, &s, &c);
+  tw[e] = make_float2((float)c, (float)s);
+}
+
+// Packs the caller's kernels [C][A][P][K*K] into tap-group order wk[g][p][lane].
+__global__ void k_pack_kernels(const float2 *__restrict__ kern, const int32_t *__restrict__ kidx,
+                               const int32_t *__restrict__ grp_chan, float2 *__restrict__ wk, int64_t n_groups,
+                               int A, int P, int KK) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // over groups x 64 lanes
+  if (i >= n_groups * 64) return;
+  const int64_t g = i >> 6;
+  const int lane = (int)(i & 63);
+  const int32_t k = kidx[i];
+  const int c = grp_chan[g];
+  for (int p = 0; p < P; ++p) {
+    float2 v = make_float2(0.f, 0.f);
+    if (k >= 0) {
+      const int a = k / KK, tap = k - a * KK;
+      v = kern[(((int64_t)c * A + a) * P + p) * KK + tap];
+    }
+    wk[(g * P + p) * 64 + lane] = v;
+  }
+}
+
+__global__ void k_fill_zero(float4 *p, int64_t n4) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+// One sample's voltages [C][A][P] -> float (re, im), exactly (int8 values are exact in FP32).
+__global__ void k_unpack_debug(const void *volt, int fmt, float2 *out, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  if (fmt == 0) {
+    const char2 v = ((const char2 *)volt)[i];
+    out[i] = make_float2((float)v.x, (float)v.y);
+  } else {
+    out[i] = ((const float2 *)volt)[i];
+  }
+}
+
+// ------------------------------------------------------------------------------------------------------------
+// Stockham stage helpers.  A stage of radix R with span L (product of the earlier radices) on an N-point
+// transform has NB = N/R butterflies; butterfly j reads x[j + m NB] (natural Stockham index), multiplies input m
+// by w_{L R}^{(j mod L) m}, applies the radix-R DFT and produces outputs at natural index
+// (j / L) L R + (j mod L) + r L.  Between stages the outputs live in LDS in a padded [r][j] layout (row stride
+// NB + 1) so that both the writes (consecutive j) and the next stage's reads avoid bank conflicts.
+// ------------------------------------------------------------------------------------------------------------
+template <int N, int R, int L>
+__device__ __forceinline__ void twiddle_dft(float2 (&x)[R], int j, const float2 *__restrict__ tw) {
+  if constexpr (L > 1) {
+    const int k = j % L;
+    constexpr int TS = N / (L * R);
+#pragma unroll
+    for (int m = 1; m < R; ++m) x[m] = cmul(x[m], tw[k * m * TS]);
+  }
+  dft<R>(x);
+}
+
+// LDS address of natural Stockham index q in the padded layout written by a stage (RP, LP); RP = 0: natural.
+template <int N, int RP, int LP>
+__device__ __forceinline__ int lds_addr(int q) {
+  if constexpr (RP == 0) {
+    return q;
+  } else {
+    constexpr int NBP = N / RP;
+    const int k = q % LP;
+    const int r = (q / LP) % RP;
+    const int j = (q / (LP * RP)) * LP + k;
+    return r * (NBP + 1) + j;
+  }
+}
+
+template <int N, int R>
+__device__ __forceinline__ int pad_addr(int j, int r) {
+  return r * (N / R + 1) + j;
+}
+
+template <int N, int R, int L>
+__device__ __forceinline__ int nat_out(int j, int r) {
+  return (j / L) * (L * R) + (j % L) + r * L;
+}
+
+template <int N> struct Pipe {
+  using F = Fac<N>;
+  static constexpr int S = F::S;
+  static constexpr int R0 = F::R0, R1 = F::R1, R2 = F::R2;
+  static constexpr int L1 = R0, L2 = R0 * R1;
+  static constexpr int RLAST = S == 2 ? R1 : R2;
+  static constexpr int LLAST = S == 2 ? L1 : L2;
+  static constexpr int RMAX = (R0 > R1 ? (R0 > R2 ? R0 : R2) : (R1 > R2 ? R1 : R2));
+  static constexpr int TS = N + RMAX + 1;   // LDS stride of one transform (odd: spreads banks across transforms)
+};
+
+// ------------------------------------------------------------------------------------------------------------
+// Row pass
+// ------------------------------------------------------------------------------------------------------------
+enum RowMode { ROW_FUSED = 0, ROW_GRID = 1, ROW_FFT = 2 };
+
+// In-LDS stage over the band's transforms (rows).  Transform tr (0..ntr) lives at buf + tr_base(tr).
+template <int N, int R, int L, int RP, int LP, int MAXB, class Base>
+__device__ __forceinline__ void row_stage_lds(float2 *buf, int ntr, const float2 *tw, Base tr_base) {
+  constexpr int NB = N / R;
+  float2 x[MAXB][R];
+  const int total = ntr * NB;
+#pragma unroll
+  for (int s = 0; s < MAXB; ++s) {
+    const int b = threadIdx.x + s * kThreads;
+    if (b < total) {
+      const int tr = b / NB, j = b - tr * NB;
+      const float2 *in = buf + tr_base(tr);
+#pragma unroll
+      for (int m = 0; m < R; ++m) x[s][m] = in[lds_addr<N, RP, LP>(j + m * NB)];
+      twiddle_dft<N, R, L>(x[s], j, tw);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < MAXB; ++s) {
+    const int b = threadIdx.x + s * kThreads;
+    if (b < total) {
+      const int tr = b / NB, j = b - tr * NB;
+      float2 *out = buf + tr_base(tr);
+#pragma unroll
+      for (int r = 0; r < R; ++r) out[pad_addr<N, R>(j, r)] = x[s][r];
+    }
+  }
+  __syncthreads();
+}
+
+// Last stage: LDS -> global rows (natural order).
+template <int N, int R, int L, int RP, int LP, int MAXB, class Base, class Dst>
+__device__ __forceinline__ void row_stage_out(const float2 *buf, int ntr, const float2 *tw, Base tr_base, Dst dst) {
+  constexpr int NB = N / R;
+  const int total = ntr * NB;
+#pragma unroll
+  for (int s = 0; s < MAXB; ++s) {
+    const int b = threadIdx.x + s * kThreads;
+    if (b < total) {
+      const int tr = b / NB, j = b - tr * NB;
+      const float2 *in = buf + tr_base(tr);
+      float2 x[R];
+#pragma unroll
+      for (int m = 0; m < R; ++m) x[m] = in[lds_addr<N, RP, LP>(j + m * NB)];
+      twiddle_dft<N, R, L>(x, j, tw);
+      float2 *o = dst(tr);
+#pragma unroll
+      for (int r = 0; r < R; ++r) o[nat_out<N, R, L>(j, r)] = x[r];
+    }
+  }
+}
+
+template <int N, int P, int MODE>
+__global__ __launch_bounds__(kThreads) void k_rows(RowArgs a) {
+  using PP = Pipe<N>;
+  constexpr int TS = PP::TS;
+  constexpr int HB = band_rows_ce(N, P);             // rows per band
+  extern __shared__ float4 smem4[];
+  const int hb = HB;
+  float2 *grid = reinterpret_cast<float2 *>(smem4);  // [P][hb][TS]
+  float2 *tws = grid + P * hb * TS;                  // [N]
+  void *vs = tws + N;                                // staged voltages of one sample, [A][P]
+
+  const int nb = a.n_bands;
+  const Band bd = a.bands[a.band_begin + (int)(blockIdx.x % nb)];
+  const int tg = (int)(blockIdx.x / nb);
+  const int c = bd.chan;
+  const int t_lo = a.t0 + tg * a.t_group;
+  const int t_hi = min(a.t0 + a.nt, t_lo + a.t_group);
+  const int nrow = bd.r_hi - bd.r_lo + 1;
+  const int ntr = P * nrow;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+
+  for (int i = threadIdx.x; i < N; i += kThreads) tws[i] = a.tw[i];
+
+  auto tr_base = [&](int tr) {
+    const int p = tr / nrow, r = tr - p * nrow;
+    return (p * hb + (bd.r_lo - bd.row0 + r)) * TS;
+  };
+
+  for (int t = t_lo; t < t_hi; ++t) {
+    if constexpr (MODE == ROW_FUSED || MODE == ROW_GRID) {
+      // stage this sample's voltage row of channel c and clear the band grid
+      const int64_t row = ((int64_t)t * a.n_chan + c) * a.n_ant * P;
+      if (a.volt_fmt == 0) {
+        const uint16_t *src = reinterpret_cast<const uint16_t *>(a.volt) + row;
+        uint16_t *dst = reinterpret_cast<uint16_t *>(vs);
+        for (int i = threadIdx.x; i < a.n_ant * P; i += kThreads) dst[i] = src[i];
+      } else {
+        const float2 *src = reinterpret_cast<const float2 *>(a.volt) + row;
+        float2 *dst = reinterpret_cast<float2 *>(vs);
+        for (int i = threadIdx.x; i < a.n_ant * P; i += kThreads) dst[i] = src[i];
+      }
+      for (int i = threadIdx.x; i < P * hb * TS; i += kThreads) grid[i] = make_float2(0.f, 0.f);
+      __syncthreads();
+      // deterministic scatter: this wavefront's tap groups, one tap per lane, distinct cells per group
+      const int64_t g0 = bd.grp_off[wave];
+      const int gc = bd.grp_cnt[wave];
+      for (int g = 0; g < gc; ++g) {
+        const uint32_t m = a.meta[(g0 + g) * 64 + lane];
+        if (m != kEmptyTap) {
+          const int ant = (int)(m >> 16), cell = (int)(m & 0xFFFFu);
+          const int rr = cell / N, col = cell - rr * N;
+#pragma unroll
+          for (int p = 0; p < P; ++p) {
+            const float2 w = a.wk[((g0 + g) * P + p) * 64 + lane];
+            float2 e;
+            if (a.volt_fmt == 0) {
+              const uint16_t v = reinterpret_cast<const uint16_t *>(vs)[ant * P + p];
+              e = make_float2((float)(int8_t)(v & 0xFF), (float)(int8_t)(v >> 8));
+            } else {
+              e = reinterpret_cast<const float2 *>(vs)[ant * P + p];
+            }
+            float2 *cellp = grid + (p * hb + rr) * TS + col;
+            const float2 cur = *cellp;
+            *cellp = make_float2(cur.x + w.x * e.x - w.y * e.y, cur.y + w.x * e.y + w.y * e.x);
+          }
+        }
+      }
+      __syncthreads();
+    } else {
+      // ROW_FFT: load the band's touched rows from the staged grid
+      for (int i = threadIdx.x; i < ntr * N; i += kThreads) {
+        const int tr = i / N, col = i - tr * N;
+        const int p = tr / nrow, r = tr - p * nrow;
+        grid[tr_base(tr) + col] =
+            a.io[(int64_t)t * a.sample_stride + (int64_t)P * a.chans[c].pix_off + (int64_t)p * N * N +
+                 (int64_t)(bd.r_lo + r) * N + col];
+      }
+      __syncthreads();
+    }
+
+    if constexpr (MODE == ROW_GRID) {
+      // write the whole band (all its rows) to the staged grid
+      for (int i = threadIdx.x; i < P * bd.rows * N; i += kThreads) {
+        const int pr = i / N, col = i - pr * N;
+        const int p = pr / bd.rows, r = pr - p * bd.rows;
+        a.io[(int64_t)t * a.sample_stride + (int64_t)P * a.chans[c].pix_off + (int64_t)p * N * N +
+             (int64_t)(bd.row0 + r) * N + col] = grid[(p * hb + r) * TS + col];
+      }
+      __syncthreads();
+    } else {
+      // row FFTs of the touched rows
+      constexpr int MB0 = (P * HB * (N / PP::R0) + kThreads - 1) / kThreads;
+      auto dst = [&](int tr) -> float2 * {
+        const int p = tr / nrow, r = tr - p * nrow;
+        if constexpr (MODE == ROW_FUSED)
+          return a.io + (((int64_t)(c - a.c0) * a.t_block + (t - a.t0)) * P + p) * N * N + (int64_t)(bd.r_lo + r) * N;
+        else
+          return a.io + (int64_t)t * a.sample_stride + (int64_t)P * a.chans[c].pix_off + (int64_t)p * N * N +
+                 (int64_t)(bd.r_lo + r) * N;
+      };
+      if constexpr (PP::S == 2) {
+        constexpr int MB1 = (P * HB * (N / PP::R1) + kThreads - 1) / kThreads;
+        row_stage_lds<N, PP::R0, 1, 0, 1, MB0>(grid, ntr, tws, tr_base);
+        row_stage_out<N, PP::R1, PP::L1, PP::R0, 1, MB1>(grid, ntr, tws, tr_base, dst);
+      } else {
+        constexpr int MB1 = (P * HB * (N / PP::R1) + kThreads - 1) / kThreads;
+        constexpr int MB2 = (P * HB * (N / PP::R2) + kThreads - 1) / kThreads;
+        row_stage_lds<N, PP::R0, 1, 0, 1, MB0>(grid, ntr, tws, tr_base);
+        row_stage_lds<N, PP::R1, PP::L1, PP::R0, 1, MB1>(grid, ntr, tws, tr_base);
+        row_stage_out<N, PP::R2, PP::L2, PP::R1, PP::L1, MB2>(grid, ntr, tws, tr_base, dst);
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------------------------
+// Column pass
+// ------------------------------------------------------------------------------------------------------------
+enum ColMode { COL_FUSED = 0, COL_FFT = 1 };
+
+template <int N, int P, int W, int MODE, int ACC>
+__global__ __launch_bounds__(kThreads) void k_cols(ColArgs a) {
+  using PP = Pipe<N>;
+  constexpr int TS = PP::TS;
+  constexpr int R0 = PP::R0, NB0 = N / R0;
+  constexpr int RL = PP::RLAST, LL = PP::LLAST, NBL = N / RL;
+  constexpr int PR = P == 2 ? 4 : 1;
+  constexpr int MBL = (W * NBL + kThreads - 1) / kThreads;
+  extern __shared__ float4 smem4[];
+  float2 *buf = reinterpret_cast<float2 *>(smem4);   // [P][W][TS]
+  float2 *tws = buf + P * W * TS;                     // [N]
+
+  // workgroup -> (channel, column group)
+  const int c = a.c0 + (int)(blockIdx.x / (N / W));
+  const int col0 = (int)(blockIdx.x % (N / W)) * W;
+  const int jmin = a.chans[c].jmin, jmax = a.chans[c].jmax;
+
+  for (int i = threadIdx.x; i < N; i += kThreads) tws[i] = a.tw[i];
+
+  float acc[MBL][RL][PR];
+#pragma unroll
+  for (int s = 0; s < MBL; ++s)
+#pragma unroll
+    for (int r = 0; r < RL; ++r)
+#pragma unroll
+      for (int k = 0; k < PR; ++k) acc[s][r][k] = 0.f;
+
+  const int per = (a.nt + (int)gridDim.y - 1) / (int)gridDim.y;
+  const int t_begin = a.t0 + (int)blockIdx.y * per;
+  const int t_end = min(a.t0 + a.nt, t_begin + per);
+  for (int t = t_begin; t < t_end; ++t) {
+    const float2 *src;
+    int64_t pstride;
+    if constexpr (MODE == COL_FUSED) {
+      src = a.in + ((int64_t)(c - a.c0) * a.t_block + (t - a.t0)) * P * N * N;
+    } else {
+      src = a.in + (int64_t)t * a.sample_stride + (int64_t)P * a.chans[c].pix_off;
+    }
+    pstride = (int64_t)N * N;
+    __syncthreads();   // previous sample's last stage has finished reading buf
+    // first stage: from global (rows outside [jmin, jmax] are zero), straight to the LDS padded layout
+    // (no barrier between read and write: the buffer is not read during this stage)
+    for (int b = threadIdx.x; b < P * W * NB0; b += kThreads) {
+      const int col = b % W, p = (b / W) % P, j = b / (W * P);
+      float2 x[R0];
+#pragma unroll
+      for (int m = 0; m < R0; ++m) {
+        const int row = j + m * NB0;
+        x[m] = (row >= jmin && row <= jmax) ? src[p * pstride + (int64_t)row * N + col0 + col]
+                                            : make_float2(0.f, 0.f);
+      }
+      dft<R0>(x);
+      float2 *o = buf + (p * W + col) * TS;
+#pragma unroll
+      for (int r = 0; r < R0; ++r) o[pad_addr<N, R0>(j, r)] = x[r];
+    }
+    __syncthreads();
+    // middle stage (3-stage pipelines)
+    if constexpr (PP::S == 3) {
+      constexpr int R1 = PP::R1, NB1 = N / R1;
+      constexpr int MB1 = (P * W * NB1 + kThreads - 1) / kThreads;
+      float2 x[MB1][R1];
+#pragma unroll
+      for (int s = 0; s < MB1; ++s) {
+        const int b = threadIdx.x + s * kThreads;
+        if (b < P * W * NB1) {
+          const int col = b % W, p = (b / W) % P, j = b / (W * P);
+          const float2 *in = buf + (p * W + col) * TS;
+#pragma unroll
+          for (int m = 0; m < R1; ++m) x[s][m] = in[lds_addr<N, R0, 1>(j + m * NB1)];
+          twiddle_dft<N, R1, PP::L1>(x[s], j, tws);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < MB1; ++s) {
+        const int b = threadIdx.x + s * kThreads;
+        if (b < P * W * NB1) {
+          const int col = b % W, p = (b / W) % P, j = b / (W * P);
+          float2 *o = buf + (p * W + col) * TS;
+#pragma unroll
+          for (int r = 0; r < R1; ++r) o[pad_addr<N, R1>(j, r)] = x[s][r];
+        }
+      }
+      __syncthreads();
+    }
+    // last stage: both pols of one (column, butterfly) in one thread
+    {
+      constexpr int RPV = PP::S == 2 ? PP::R0 : PP::R1;
+      constexpr int LPV = PP::S == 2 ? 1 : PP::L1;
+#pragma unroll
+      for (int s = 0; s < MBL; ++s) {
+        const int b = threadIdx.x + s * kThreads;
+        if (b < W * NBL) {
+          const int col = b % W, j = b / W;
+          float2 x[P][RL];
+#pragma unroll
+          for (int p = 0; p < P; ++p) {
+            const float2 *in = buf + (p * W + col) * TS;
+#pragma unroll
+            for (int m = 0; m < RL; ++m) x[p][m] = in[lds_addr<N, RPV, LPV>(j + m * NBL)];
+            twiddle_dft<N, RL, LL>(x[p], j, tws);
+          }
+          if constexpr (MODE == COL_FUSED) {
+#pragma unroll
+            for (int r = 0; r < RL; ++r) {
+              const float2 ex = x[0][r];
+              if constexpr (P == 2) {
+                const float2 ey = x[1][r];
+                acc[s][r][0] += ex.x * ex.x + ex.y * ex.y;
+                acc[s][r][1] += ey.x * ey.x + ey.y * ey.y;
+                acc[s][r][2] += ex.x * ey.x + ex.y * ey.y;   // Re(E_X conj E_Y)
+                acc[s][r][3] += ex.y * ey.x - ex.x * ey.y;   // Im(E_X conj E_Y)
+              } else {
+                acc[s][r][0] += ex.x * ex.x + ex.y * ex.y;
+              }
+            }
+          } else {
+            float2 *dst = a.out + (int64_t)t * a.sample_stride + (int64_t)P * a.chans[c].pix_off;
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+#pragma unroll
+              for (int r = 0; r < RL; ++r) {
+                const int q = nat_out<N, RL, LL>(j, r);
+                dst[p * pstride + (int64_t)q * N + col0 + col] = x[p][r];
+              }
+          }
+        }
+      }
+    }
+  }
+
+  if constexpr (MODE == COL_FUSED) {
+    // add the block's FP32 partial sums to the accumulator, one writer per pixel
+    const int64_t base = (int64_t)PR * a.chans[c].pix_off;
+#pragma unroll
+    for (int s = 0; s < MBL; ++s) {
+      const int b = threadIdx.x + s * kThreads;
+      if (b < W * NBL) {
+        const int col = b % W, j = b / W;
+#pragma unroll
+        for (int r = 0; r < RL; ++r) {
+          const int q = nat_out<N, RL, LL>(j, r);
+#pragma unroll
+          for (int k = 0; k < PR; ++k) {
+            const int64_t idx = base + (int64_t)k * N * N + (int64_t)q * N + col0 + col;
+            if constexpr (ACC == 0) {
+              float *o = reinterpret_cast<float *>(a.acc);
+              o[idx] += acc[s][r][k];
+            } else {
+              // Neumaier compensated summation in FP64: (sum, carry)
+              double2 *o = reinterpret_cast<double2 *>(a.acc);
+              double2 sc = o[idx];
+              const double xv = (double)acc[s][r][k];
+              const double tsum = sc.x + xv;
+              if (fabs(sc.x) >= fabs(xv))
+                sc.y += (sc.x - tsum) + xv;
+              else
+                sc.y += (xv - tsum) + sc.x;
+              sc.x = tsum;
+              o[idx] = sc;
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------------------------
+// Staged accumulate: E-field images -> products, summed over the n_t samples, added to the accumulator.
+// ------------------------------------------------------------------------------------------------------------
+template <int P, int ACC>
+__global__ void k_acc_staged(AccArgs a) {
+  const int64_t pix = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (pix >= a.pix_total) return;
+  // channel of this pixel
+  int c = 0;
+  while (c + 1 < a.n_chan && a.chans[c + 1].pix_off <= pix) ++c;
+  const int64_t local = pix - a.chans[c].pix_off;
+  const int64_t nn = (int64_t)a.chans[c].n * a.chans[c].n;
+  constexpr int PR = P == 2 ? 4 : 1;
+  float s[PR];
+#pragma unroll
+  for (int k = 0; k < PR; ++k) s[k] = 0.f;
+  for (int64_t t = 0; t < a.nt; ++t) {
+    const float2 *e = a.efield + t * a.sample_stride + (int64_t)P * a.chans[c].pix_off + local;
+    const float2 ex = e[0];
+    if constexpr (P == 2) {
+      const float2 ey = e[nn];
+      s[0] += ex.x * ex.x + ex.y * ex.y;
+      s[1] += ey.x * ey.x + ey.y * ey.y;
+      s[2] += ex.x * ey.x + ex.y * ey.y;
+      s[3] += ex.y * ey.x - ex.x * ey.y;
+    } else {
+      s[0] += ex.x * ex.x + ex.y * ex.y;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < PR; ++k) {
+    const int64_t idx = (int64_t)PR * a.chans[c].pix_off + k * nn + local;
+    if constexpr (ACC == 0) {
+      reinterpret_cast<float *>(a.acc)[idx] += s[k];
+    } else {
+      double2 *o = reinterpret_cast<double2 *>(a.acc);
+      double2 sc = o[idx];
+      const double xv = (double)s[k];
+      const double tsum = sc.x + xv;
+      if (fabs(sc.x) >= fabs(xv))
+        sc.y += (sc.x - tsum) + xv;
+      else
+        sc.y += (xv - tsum) + sc.x;
+      sc.x = tsum;
+      o[idx] = sc;
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------------------------
+// Read-out: accumulator (FFT pixel order) -> centred complex64 image, products XX, YY, XY, YX.
+// ------------------------------------------------------------------------------------------------------------
+template <int P, int ACC>
+__global__ void k_read_image(ReadArgs a) {
+  const int64_t pix = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // over output pixels of all channels
+  if (pix >= a.pix_total) return;
+  int c = 0;
+  while (c + 1 < a.n_chan && a.chans[c + 1].pix_off <= pix) ++c;
+  const int64_t local = pix - a.chans[c].pix_off;
+  const int n = a.chans[c].n;
+  const int64_t nn = (int64_t)n * n;
+  const int q = (int)(local / n), pcol = (int)(local - (int64_t)q * n);
+  // output pixel (q, p) <- FFT index ((q - n/2) mod n, (p - n/2) mod n)
+  const int kq = (q + n / 2) % n, kp = (pcol + n / 2) % n;
+  const int64_t src = (int64_t)kq * n + kp;
+  constexpr int PR = P == 2 ? 4 : 1;
+  const int64_t abase = (int64_t)PR * a.chans[c].pix_off;
+  double v[PR];
+#pragma unroll
+  for (int k = 0; k < PR; ++k) {
+    if constexpr (ACC == 0) {
+      v[k] = (double)reinterpret_cast<const float *>(a.acc)[abase + k * nn + src];
+    } else {
+      const double2 sc = reinterpret_cast<const double2 *>(a.acc)[abase + k * nn + src];
+      v[k] = sc.x + sc.y;
+    }
+    v[k] *= a.scale;
+  }
+  float2 *o = a.img + (int64_t)PR * a.chans[c].pix_off;
+  if constexpr (P == 2) {
+    o[0 * nn + local] = make_float2((float)v[0], 0.f);
+    o[1 * nn + local] = make_float2((float)v[1], 0.f);
+    o[2 * nn + local] = make_float2((float)v[2], (float)v[3]);
+    o[3 * nn + local] = make_float2((float)v[2], -(float)v[3]);
+  } else {
+    o[local] = make_float2((float)v[0], 0.f);
+  }
+}
+
+// ------------------------------------------------------------------------------------------------------------
+// Launchers
+// ------------------------------------------------------------------------------------------------------------
+size_t rows_lds_bytes(int n, int P, int band_rows, int A, int volt_fmt) {
+  int ts = 0;
+  switch (n) {
+#define TSCASE(NN) \
+  case NN: ts = Pipe<NN>::TS; break;
+    TSCASE(32) TSCASE(64) TSCASE(96) TSCASE(128) TSCASE(160) TSCASE(192) TSCASE(256) TSCASE(320) TSCASE(384)
+    TSCASE(512)
+#undef TSCASE
+    default: return 0;
+  }
+  const size_t vbytes = (size_t)A * P * (volt_fmt == 0 ? 2 : 8);
+  return (size_t)P * band_rows * ts * 8 + (size_t)n * 8 + ((vbytes + 15) & ~(size_t)15);
+}
+
+size_t cols_lds_bytes(int n, int P, int W) {
+  int ts = 0;
+  switch (n) {
+#define TSCASE(NN) \
+  case NN: ts = Pipe<NN>::TS; break;
+    TSCASE(32) TSCASE(64) TSCASE(96) TSCASE(128) TSCASE(160) TSCASE(192) TSCASE(256) TSCASE(320) TSCASE(384)
+    TSCASE(512)
+#undef TSCASE
+    default: return 0;
+  }
+  return (size_t)P * W * ts * 8 + (size_t)n * 8;
+}
+
+// Raises a kernel's dynamic LDS limit to the CU's 160 KB once per kernel and device.
+static hipError_t set_lds_limit(const void *fn) {
+  static std::mutex mu;
+  static std::set<std::pair<const void *, int>> done;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(mu);
+  if (done.count({fn, dev})) return hipSuccess;
+  e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+  if (e == hipSuccess) done.insert({fn, dev});
+  return e;
+}
+
+template <int N, int P>
+static hipError_t launch_rows_np(int mode, const RowArgs &a, int grid, size_t lds, hipStream_t st) {
+  void (*fn)(RowArgs) = mode == ROW_FUSED ? k_rows<N, P, ROW_FUSED> : mode == ROW_GRID ? k_rows<N, P, ROW_GRID>
+                                                                                         : k_rows<N, P, ROW_FFT>;
+  hipError_t e = set_lds_limit((const void *)fn);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(kThreads), lds, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_rows(int n, int P, int mode, const RowArgs &a, int grid, size_t lds, hipStream_t st) {
+  if (grid <= 0) return hipSuccess;
+#define RCASE(NN)                                                                                \
+  case NN:                                                                                       \
+    return P == 2 ? launch_rows_np<NN, 2>(mode, a, grid, lds, st) : launch_rows_np<NN, 1>(mode, a, grid, lds, st);
+  switch (n) {
+    RCASE(32) RCASE(64) RCASE(96) RCASE(128) RCASE(160) RCASE(192) RCASE(256) RCASE(320) RCASE(384) RCASE(512)
+    default: return hipErrorInvalidValue;
+  }
+#undef RCASE
+}
+
+template <int N, int P, int W>
+static hipError_t launch_cols_npw(int mode, int accm, const ColArgs &a, int grid, int gridy, size_t lds,
+                                  hipStream_t st) {
+  void (*fn)(ColArgs) = mode == COL_FFT ? k_cols<N, P, W, COL_FFT, 0>
+                                        : (accm == 0 ? k_cols<N, P, W, COL_FUSED, 0> : k_cols<N, P, W, COL_FUSED, 1>);
+  hipError_t e = set_lds_limit((const void *)fn);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(fn, dim3(grid, gridy), dim3(kThreads), lds, st, a);
+  return hipGetLastError();
+}
+
+template <int N, int W>
+static hipError_t launch_cols_nw(int P, int mode, int accm, const ColArgs &a, int grid, int gridy, size_t lds,
+                                 hipStream_t st) {
+  return P == 2 ? launch_cols_npw<N, 2, W>(mode, accm, a, grid, gridy, lds, st)
+                : launch_cols_npw<N, 1, W>(mode, accm, a, grid, gridy, lds, st);
+}
+
+hipError_t launch_cols(int n, int P, int W, int mode, int accm, const ColArgs &a, int grid, int gridy, size_t lds,
+                       hipStream_t st) {
+  if (grid <= 0 || gridy <= 0) return hipSuccess;
+  // (n, W) pairs follow cols_for(n)
+  switch (n) {
+    case 32: return W == 32 ? launch_cols_nw<32, 32>(P, mode, accm, a, grid, gridy, lds, st) : hipErrorInvalidValue;
+    case 64: return W == 64 ? launch_cols_nw<64, 64>(P, mode, accm, a, grid, gridy, lds, st) : hipErrorInvalidValue;
+    case 96: return W == 32 ? launch_cols_nw<96, 32>(P, mode, accm, a, grid, gridy, lds, st) : hipErrorInvalidValue;
+    case 128: return W == 32 ? launch_cols_nw<128, 32>(P, mode, accm, a, grid, gridy, lds, st) : hipErrorInvalidValue;
+    case 160: return W == 16 ? launch_cols_nw<160, 16>(P, mode, accm, a, grid, gridy, lds, st) : hipErrorInvalidValue;
+    case 192: return W == 16 ? launch_cols_nw<192, 16>(P, mode, accm, a, grid, gridy, lds, st) : hipErrorInvalidValue;
+    case 256: return W == 16 ? launch_cols_nw<256, 16>(P, mode, accm, a, grid, gridy, lds, st) : hipErrorInvalidValue;
+    case 320: return W == 8 ? launch_cols_nw<320, 8>(P, mode, accm, a, grid, gridy, lds, st) : hipErrorInvalidValue;
+    case 384: return W == 8 ? launch_cols_nw<384, 8>(P, mode, accm, a, grid, gridy, lds, st) : hipErrorInvalidValue;
+    case 512: return W == 8 ? launch_cols_nw<512, 8>(P, mode, accm, a, grid, gridy, lds, st) : hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_acc_staged(int P, int accm, const AccArgs &a, hipStream_t st) {
+  const int grid = (int)((a.pix_total + 255) / 256);
+  if (grid <= 0) return hipSuccess;
+  void (*fn)(AccArgs) = P == 2 ? (accm == 0 ? k_acc_staged<2, 0> : k_acc_staged<2, 1>)
+                               : (accm == 0 ? k_acc_staged<1, 0> : k_acc_staged<1, 1>);
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_read_image(int P, int accm, const ReadArgs &a, hipStream_t st) {
+  const int grid = (int)((a.pix_total + 255) / 256);
+  if (grid <= 0) return hipSuccess;
+  void (*fn)(ReadArgs) = P == 2 ? (accm == 0 ? k_read_image<2, 0> : k_read_image<2, 1>)
+                                : (accm == 0 ? k_read_image<1, 0> : k_read_image<1, 1>);
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_twiddle(float2 *tw, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_twiddle_f64, dim3((n + 255) / 256), dim3(256), 0, st, tw, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_kernels(const float2 *kern, const int32_t *kidx, const int32_t *grp_chan, float2 *wk,
+                               int64_t n_groups, int A, int P, int KK, hipStream_t st) {
+  const int64_t total = n_groups * 64;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pack_kernels, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, kern, kidx,
+                     grp_chan, wk, n_groups, A, P, KK);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t st) {
+  const int64_t n4 = (int64_t)(bytes / 16);
+  if (n4 == 0) return hipSuccess;
+  const int grid = (int)std::min<int64_t>((n4 + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_fill_zero, dim3(grid), dim3(256), 0, st, (float4 *)p, n4);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack_debug(const void *volt, int fmt, float2 *out, int64_t count, hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_unpack_debug, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, volt, fmt, out,
+                     count);
+  return hipGetLastError();
+}
+
+}  // namespace moff

@@ -1,0 +1,456 @@
+// C ABI of the MOFF hot path (declared in include/moff.h): validation on the host, then kernel launches on the
+// caller's stream.  Device memory is always caller-owned.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "kernels.h"
+#include "moff.h"
+#include "moff_plan.h"
+
+struct moff_plan_s {
+  moff::Plan p;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+moff_status set_err(moff_status s, const std::string &msg) {
+  g_err = msg;
+  return s;
+}
+
+moff_status ok() {
+  g_err.clear();
+  return MOFF_OK;
+}
+
+moff_status hip_fail(hipError_t e, const char *what) {
+  return set_err(MOFF_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                       \
+  do {                                            \
+    hipError_t e_ = (expr);                       \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+char *ws(const moff::Plan &p, size_t off) { return static_cast<char *>(p.d_ws) + off; }
+
+const moff::Band *d_bands(const moff::Plan &p) { return reinterpret_cast<const moff::Band *>(ws(p, p.ws_bands)); }
+const moff::Chan *d_chans(const moff::Plan &p) { return reinterpret_cast<const moff::Chan *>(ws(p, p.ws_chans)); }
+
+const float2 *d_tw(const moff::Plan &p, int n) {
+  for (size_t i = 0; i < p.tw_sizes.size(); ++i)
+    if (p.tw_sizes[i] == n) return reinterpret_cast<const float2 *>(ws(p, p.tw_off[i]));
+  return nullptr;
+}
+
+moff_status need_bound(const moff::Plan &p, bool kernels) {
+  if (!p.bound) return set_err(MOFF_E_STATE, "plan is not bound to a workspace (moff_bind)");
+  if (kernels && !p.kernels_set) return set_err(MOFF_E_STATE, "kernels are not set (moff_set_kernels)");
+  return MOFF_OK;
+}
+
+moff::RowArgs row_args(const moff::Plan &p, const void *volt) {
+  moff::RowArgs a{};
+  a.bands = d_bands(p);
+  a.chans = d_chans(p);
+  a.n_chan = p.n_chan;
+  a.n_ant = p.n_ant;
+  a.volt = volt;
+  a.volt_fmt = p.volt_format;
+  a.meta = reinterpret_cast<const uint32_t *>(ws(p, p.ws_meta));
+  a.wk = reinterpret_cast<const float2 *>(ws(p, p.ws_wk));
+  a.t_group = p.t_group;
+  a.t_block = p.t_block;
+  a.sample_stride = (int64_t)p.n_pol * p.pix_total;
+  return a;
+}
+
+// Event pair around one launch when profiling is on.
+struct ProfScope {
+  moff::Plan &p;
+  hipStream_t st;
+  moff::Plan::ProfRec rec{};
+  bool on;
+  hipError_t err = hipSuccess;
+  ProfScope(moff::Plan &pl, hipStream_t s, int kind, int64_t cs) : p(pl), st(s), on(pl.profiling) {
+    if (!on) return;
+    rec.kind = kind;
+    rec.cs = cs;
+    rec.ev0 = take();
+    rec.ev1 = take();
+    if (rec.ev0 && rec.ev1) err = hipEventRecord(static_cast<hipEvent_t>(rec.ev0), st);
+  }
+  void *take() {
+    if (p.ev_used == p.ev_pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      p.ev_pool.push_back(e);
+    }
+    return p.ev_pool[p.ev_used++];
+  }
+  hipError_t done() {
+    if (!on || !rec.ev0 || !rec.ev1) return err;
+    if (err == hipSuccess) err = hipEventRecord(static_cast<hipEvent_t>(rec.ev1), st);
+    if (err == hipSuccess) p.prof.push_back(rec);
+    return err;
+  }
+};
+
+int band_begin(const moff::Plan &p, const moff::Block &b) { return p.chans[b.c0].band_first; }
+int band_count(const moff::Plan &p, const moff::Block &b) {
+  return p.chans[b.c1 - 1].band_first + p.chans[b.c1 - 1].band_count - p.chans[b.c0].band_first;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *moff_status_str(moff_status s) {
+  switch (s) {
+    case MOFF_OK: return "MOFF_OK";
+    case MOFF_E_INVALID: return "MOFF_E_INVALID";
+    case MOFF_E_BUDGET: return "MOFF_E_BUDGET";
+    case MOFF_E_DEVICE: return "MOFF_E_DEVICE";
+    case MOFF_E_UNSUPPORTED: return "MOFF_E_UNSUPPORTED";
+    case MOFF_E_STATE: return "MOFF_E_STATE";
+  }
+  return "MOFF_E_UNKNOWN";
+}
+
+const char *moff_last_error(void) { return g_err.c_str(); }
+
+moff_status moff_plan(const moff_plan_desc *desc, moff_plan_t *out) {
+  if (!desc || !out) return set_err(MOFF_E_INVALID, "null argument");
+  moff_plan_s *h = new (std::nothrow) moff_plan_s();
+  if (!h) return set_err(MOFF_E_INVALID, "out of host memory");
+  std::string err;
+  moff_status s = moff::build_plan(*desc, h->p, &err);
+  if (s != MOFF_OK) {
+    delete h;
+    return set_err(s, err);
+  }
+  const moff::Plan &p = h->p;
+  const size_t vb = (size_t)p.n_ant * p.n_pol * (p.volt_format == MOFF_VOLT_INT8 ? 2 : 8);
+  for (const moff::Chan &c : p.chans) {
+    if (moff::rows_lds_bytes(c.n, p.n_pol, c.band_rows, p.n_ant, p.volt_format) > (size_t)moff::kMaxLds ||
+        vb > 64 * 1024) {
+      delete h;
+      return set_err(MOFF_E_UNSUPPORTED, "one sample's voltages of a channel exceed the 64 KB LDS staging area");
+    }
+  }
+  *out = h;
+  return ok();
+}
+
+void moff_plan_destroy(moff_plan_t plan) {
+  if (!plan) return;
+  for (void *e : plan->p.ev_pool) (void)hipEventDestroy(static_cast<hipEvent_t>(e));
+  delete plan;
+}
+
+moff_status moff_workspace_size(moff_plan_t plan, size_t *bytes) {
+  if (!plan || !bytes) return set_err(MOFF_E_INVALID, "null argument");
+  *bytes = plan->p.ws_total;
+  return ok();
+}
+
+moff_status moff_acc_size(moff_plan_t plan, size_t *bytes) {
+  if (!plan || !bytes) return set_err(MOFF_E_INVALID, "null argument");
+  const moff::Plan &p = plan->p;
+  *bytes = (size_t)p.pix_total * p.acc_reals() * p.acc_elem_bytes();
+  return ok();
+}
+
+moff_status moff_image_size(moff_plan_t plan, size_t *bytes) {
+  if (!plan || !bytes) return set_err(MOFF_E_INVALID, "null argument");
+  *bytes = (size_t)plan->p.pix_total * plan->p.n_prod() * 8;
+  return ok();
+}
+
+moff_status moff_grid_n(moff_plan_t plan, int32_t chan, int32_t *n) {
+  if (!plan || !n) return set_err(MOFF_E_INVALID, "null argument");
+  if (chan < 0 || chan >= plan->p.n_chan) return set_err(MOFF_E_INVALID, "channel out of range");
+  *n = plan->p.chans[chan].n;
+  return ok();
+}
+
+moff_status moff_chan_offset(moff_plan_t plan, int32_t chan, int64_t *pix_off) {
+  if (!plan || !pix_off) return set_err(MOFF_E_INVALID, "null argument");
+  if (chan < 0 || chan >= plan->p.n_chan) return set_err(MOFF_E_INVALID, "channel out of range");
+  *pix_off = plan->p.chans[chan].pix_off;
+  return ok();
+}
+
+moff_status moff_bind(moff_plan_t plan, void *d_ws, size_t bytes, void *stream) {
+  if (!plan || !d_ws) return set_err(MOFF_E_INVALID, "null argument");
+  moff::Plan &p = plan->p;
+  if (bytes < p.ws_total) return set_err(MOFF_E_BUDGET, "workspace smaller than moff_workspace_size");
+  if (reinterpret_cast<uintptr_t>(d_ws) & 255) return set_err(MOFF_E_INVALID, "workspace must be 256-byte aligned");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  p.d_ws = d_ws;
+  p.bound = false;
+  p.kernels_set = false;
+  if (!p.bands.empty())
+    HIP_TRY(hipMemcpyAsync(ws(p, p.ws_bands), p.bands.data(), p.bands.size() * sizeof(moff::Band),
+                           hipMemcpyHostToDevice, st), "upload bands");
+  HIP_TRY(hipMemcpyAsync(ws(p, p.ws_chans), p.chans.data(), p.chans.size() * sizeof(moff::Chan),
+                         hipMemcpyHostToDevice, st), "upload channels");
+  if (p.n_groups) {
+    HIP_TRY(hipMemcpyAsync(ws(p, p.ws_meta), p.grp_meta.data(), p.grp_meta.size() * 4, hipMemcpyHostToDevice, st),
+            "upload tap groups");
+    HIP_TRY(hipMemcpyAsync(ws(p, p.ws_kidx), p.grp_kidx.data(), p.grp_kidx.size() * 4, hipMemcpyHostToDevice, st),
+            "upload tap indices");
+    HIP_TRY(hipMemcpyAsync(ws(p, p.ws_gchan), p.grp_chan.data(), p.grp_chan.size() * 4, hipMemcpyHostToDevice, st),
+            "upload group channels");
+  }
+  for (size_t i = 0; i < p.tw_sizes.size(); ++i)
+    HIP_TRY(moff::launch_twiddle(reinterpret_cast<float2 *>(ws(p, p.tw_off[i])), p.tw_sizes[i], st), "twiddles");
+  p.bound = true;
+  return ok();
+}
+
+moff_status moff_set_kernels(moff_plan_t plan, const void *d_kern, void *stream) {
+  if (!plan || !d_kern) return set_err(MOFF_E_INVALID, "null argument");
+  moff::Plan &p = plan->p;
+  moff_status s = need_bound(p, false);
+  if (s) return s;
+  HIP_TRY(moff::launch_pack_kernels(static_cast<const float2 *>(d_kern),
+                                    reinterpret_cast<const int32_t *>(ws(p, p.ws_kidx)),
+                                    reinterpret_cast<const int32_t *>(ws(p, p.ws_gchan)),
+                                    reinterpret_cast<float2 *>(ws(p, p.ws_wk)), p.n_groups, p.n_ant, p.n_pol,
+                                    p.ksize * p.ksize, static_cast<hipStream_t>(stream)),
+          "pack kernels");
+  p.kernels_set = true;
+  return ok();
+}
+
+moff_status moff_grid(moff_plan_t plan, const void *d_volt, int64_t n_t, void *d_grid, void *stream) {
+  if (!plan) return set_err(MOFF_E_INVALID, "null plan");
+  if (n_t < 0) return set_err(MOFF_E_INVALID, "n_t must be >= 0");
+  if (n_t > 0 && (!d_volt || !d_grid)) return set_err(MOFF_E_INVALID, "null buffer");
+  moff::Plan &p = plan->p;
+  moff_status s = need_bound(p, true);
+  if (s) return s;
+  if (n_t == 0) return ok();
+  if (n_t > INT32_MAX / 2) return set_err(MOFF_E_INVALID, "n_t too large for one call");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  HIP_TRY(moff::launch_fill_zero(d_grid, (size_t)n_t * p.n_pol * p.pix_total * 8, st), "clear grid");
+  moff::RowArgs a = row_args(p, d_volt);
+  a.io = static_cast<float2 *>(d_grid);
+  a.t0 = 0;
+  a.nt = (int)n_t;
+  for (const moff::Block &b : p.blocks) {
+    a.band_begin = band_begin(p, b);
+    a.n_bands = band_count(p, b);
+    a.c0 = b.c0;
+    a.tw = d_tw(p, b.n);
+    const int tgroups = (int)((n_t + p.t_group - 1) / p.t_group);
+    const size_t lds = moff::rows_lds_bytes(b.n, p.n_pol, p.chans[b.c0].band_rows, p.n_ant, p.volt_format);
+    HIP_TRY(moff::launch_rows(b.n, p.n_pol, moff::ROW_MODE_GRID, a, a.n_bands * tgroups, lds, st), "grid");
+  }
+  return ok();
+}
+
+moff_status moff_fft(moff_plan_t plan, void *d_grid, int64_t n_t, void *stream) {
+  if (!plan) return set_err(MOFF_E_INVALID, "null plan");
+  if (n_t < 0) return set_err(MOFF_E_INVALID, "n_t must be >= 0");
+  if (n_t > 0 && !d_grid) return set_err(MOFF_E_INVALID, "null buffer");
+  moff::Plan &p = plan->p;
+  moff_status s = need_bound(p, false);
+  if (s) return s;
+  if (n_t == 0) return ok();
+  if (n_t > INT32_MAX / 2) return set_err(MOFF_E_INVALID, "n_t too large for one call");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  moff::RowArgs a = row_args(p, nullptr);
+  a.io = static_cast<float2 *>(d_grid);
+  a.t0 = 0;
+  a.nt = (int)n_t;
+  moff::ColArgs ca{};
+  ca.chans = d_chans(p);
+  ca.in = static_cast<const float2 *>(d_grid);
+  ca.out = static_cast<float2 *>(d_grid);
+  ca.t0 = 0;
+  ca.nt = (int)n_t;
+  ca.t_block = 0;
+  ca.sample_stride = (int64_t)p.n_pol * p.pix_total;
+  for (const moff::Block &b : p.blocks) {
+    a.band_begin = band_begin(p, b);
+    a.n_bands = band_count(p, b);
+    a.c0 = b.c0;
+    a.tw = d_tw(p, b.n);
+    const int tgroups = (int)((n_t + p.t_group - 1) / p.t_group);
+    const size_t lds = moff::rows_lds_bytes(b.n, p.n_pol, p.chans[b.c0].band_rows, p.n_ant, p.volt_format);
+    HIP_TRY(moff::launch_rows(b.n, p.n_pol, moff::ROW_MODE_FFT, a, a.n_bands * tgroups, lds, st), "row fft");
+  }
+  for (const moff::Block &b : p.blocks) {
+    const int W = p.chans[b.c0].cols;
+    ca.c0 = b.c0;
+    ca.tw = d_tw(p, b.n);
+    const int grid = (b.c1 - b.c0) * (b.n / W);
+    HIP_TRY(moff::launch_cols(b.n, p.n_pol, W, moff::COL_MODE_FFT, 0, ca, grid, (int)n_t,
+                              moff::cols_lds_bytes(b.n, p.n_pol, W), st),
+            "column fft");
+  }
+  return ok();
+}
+
+moff_status moff_accumulate(moff_plan_t plan, const void *d_efield, int64_t n_t, void *d_acc, void *stream) {
+  if (!plan) return set_err(MOFF_E_INVALID, "null plan");
+  if (n_t < 0) return set_err(MOFF_E_INVALID, "n_t must be >= 0");
+  if (n_t > 0 && (!d_efield || !d_acc)) return set_err(MOFF_E_INVALID, "null buffer");
+  moff::Plan &p = plan->p;
+  moff_status s = need_bound(p, false);
+  if (s) return s;
+  if (n_t == 0) return ok();
+  moff::AccArgs a{};
+  a.chans = d_chans(p);
+  a.n_chan = p.n_chan;
+  a.pix_total = p.pix_total;
+  a.nt = n_t;
+  a.efield = static_cast<const float2 *>(d_efield);
+  a.sample_stride = (int64_t)p.n_pol * p.pix_total;
+  a.acc = d_acc;
+  HIP_TRY(moff::launch_acc_staged(p.n_pol, p.acc_mode, a, static_cast<hipStream_t>(stream)), "accumulate");
+  return ok();
+}
+
+moff_status moff_correlate(moff_plan_t plan, const void *d_volt, int64_t n_t, void *d_acc, void *stream) {
+  if (!plan) return set_err(MOFF_E_INVALID, "null plan");
+  if (n_t < 0) return set_err(MOFF_E_INVALID, "n_t must be >= 0");
+  if (n_t > 0 && (!d_volt || !d_acc)) return set_err(MOFF_E_INVALID, "null buffer");
+  moff::Plan &p = plan->p;
+  moff_status s = need_bound(p, true);
+  if (s) return s;
+  if (n_t == 0) return ok();
+  if (n_t > INT32_MAX / 2) return set_err(MOFF_E_INVALID, "n_t too large for one call");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  float2 *H = reinterpret_cast<float2 *>(ws(p, p.ws_h));
+  moff::RowArgs a = row_args(p, d_volt);
+  a.io = H;
+  moff::ColArgs ca{};
+  ca.chans = d_chans(p);
+  ca.in = H;
+  ca.acc = d_acc;
+  ca.t_block = p.t_block;
+  for (int64_t t0 = 0; t0 < n_t; t0 += p.t_block) {
+    const int nt = (int)std::min<int64_t>(p.t_block, n_t - t0);
+    for (const moff::Block &b : p.blocks) {
+      a.band_begin = band_begin(p, b);
+      a.n_bands = band_count(p, b);
+      a.c0 = b.c0;
+      a.t0 = (int)t0;
+      a.nt = nt;
+      a.tw = d_tw(p, b.n);
+      const int tgroups = (nt + p.t_group - 1) / p.t_group;
+      const size_t lds = moff::rows_lds_bytes(b.n, p.n_pol, p.chans[b.c0].band_rows, p.n_ant, p.volt_format);
+      const int64_t cs = (int64_t)nt * (b.c1 - b.c0);
+      {
+        ProfScope ps(p, st, 0, cs);
+        HIP_TRY(moff::launch_rows(b.n, p.n_pol, moff::ROW_MODE_FUSED, a, a.n_bands * tgroups, lds, st), "row pass");
+        HIP_TRY(ps.done(), "profile event");
+      }
+      const int W = p.chans[b.c0].cols;
+      ca.c0 = b.c0;
+      ca.t0 = (int)t0;
+      ca.nt = nt;
+      ca.tw = a.tw;
+      const int grid = (b.c1 - b.c0) * (b.n / W);
+      {
+        ProfScope ps(p, st, 1, cs);
+        HIP_TRY(moff::launch_cols(b.n, p.n_pol, W, moff::COL_MODE_FUSED, p.acc_mode, ca, grid, 1,
+                                  moff::cols_lds_bytes(b.n, p.n_pol, W), st),
+                "column pass");
+        HIP_TRY(ps.done(), "profile event");
+      }
+    }
+  }
+  return ok();
+}
+
+moff_status moff_read_image(moff_plan_t plan, const void *d_acc, int64_t n_samples, int32_t normalize, void *d_img,
+                            void *stream) {
+  if (!plan || !d_acc || !d_img) return set_err(MOFF_E_INVALID, "null argument");
+  if (normalize && n_samples <= 0) return set_err(MOFF_E_INVALID, "normalize needs n_samples > 0");
+  moff::Plan &p = plan->p;
+  moff_status s = need_bound(p, false);
+  if (s) return s;
+  moff::ReadArgs a{};
+  a.chans = d_chans(p);
+  a.n_chan = p.n_chan;
+  a.pix_total = p.pix_total;
+  a.acc = d_acc;
+  a.scale = normalize ? 1.0 / (double)n_samples : 1.0;
+  a.img = static_cast<float2 *>(d_img);
+  HIP_TRY(moff::launch_read_image(p.n_pol, p.acc_mode, a, static_cast<hipStream_t>(stream)), "read image");
+  return ok();
+}
+
+moff_status moff_profile(moff_plan_t plan, int32_t enable) {
+  if (!plan) return set_err(MOFF_E_INVALID, "null plan");
+  moff::Plan &p = plan->p;
+  p.profiling = enable != 0;
+  if (p.profiling) {
+    p.prof.clear();
+    p.ev_used = 0;
+  }
+  return ok();
+}
+
+moff_status moff_profile_read(moff_plan_t plan, int32_t kind, double *total_ms, int64_t *launches,
+                              int64_t *channel_samples) {
+  if (!plan) return set_err(MOFF_E_INVALID, "null plan");
+  moff::Plan &p = plan->p;
+  double ms = 0.0;
+  int64_t n = 0, cs = 0;
+  for (const moff::Plan::ProfRec &r : p.prof) {
+    if (r.kind != kind) continue;
+    float e = 0.f;
+    HIP_TRY(hipEventSynchronize(static_cast<hipEvent_t>(r.ev1)), "profile sync");
+    HIP_TRY(hipEventElapsedTime(&e, static_cast<hipEvent_t>(r.ev0), static_cast<hipEvent_t>(r.ev1)),
+            "profile elapsed");
+    ms += e;
+    ++n;
+    cs += r.cs;
+  }
+  if (total_ms) *total_ms = ms;
+  if (launches) *launches = n;
+  if (channel_samples) *channel_samples = cs;
+  return ok();
+}
+
+moff_status moff_debug_unpack(moff_plan_t plan, const void *d_volt, float *d_out, void *stream) {
+  if (!plan || !d_volt || !d_out) return set_err(MOFF_E_INVALID, "null argument");
+  const moff::Plan &p = plan->p;
+  HIP_TRY(moff::launch_unpack_debug(d_volt, p.volt_format, reinterpret_cast<float2 *>(d_out),
+                                    (int64_t)p.n_chan * p.n_ant * p.n_pol, static_cast<hipStream_t>(stream)),
+          "unpack");
+  return ok();
+}
+
+moff_status moff_debug_tile_counts(moff_plan_t plan, int64_t *n_band_total, int64_t *n_entries, int32_t *band_rows) {
+  if (!plan) return set_err(MOFF_E_INVALID, "null plan");
+  const moff::Plan &p = plan->p;
+  if (n_band_total) *n_band_total = (int64_t)p.bands.size();
+  if (n_entries) *n_entries = (int64_t)p.band_ant.size();
+  if (band_rows)
+    for (int c = 0; c < p.n_chan; ++c) band_rows[c] = p.chans[c].band_rows;
+  return ok();
+}
+
+moff_status moff_debug_tiles(moff_plan_t plan, int32_t *h_origin, int32_t *h_band_ptr, int32_t *h_band_ant) {
+  if (!plan) return set_err(MOFF_E_INVALID, "null plan");
+  const moff::Plan &p = plan->p;
+  if (h_origin) std::memcpy(h_origin, p.origin.data(), p.origin.size() * 4);
+  if (h_band_ptr) std::memcpy(h_band_ptr, p.band_ptr.data(), p.band_ptr.size() * 4);
+  if (h_band_ant && !p.band_ant.empty()) std::memcpy(h_band_ant, p.band_ant.data(), p.band_ant.size() * 4);
+  return ok();
+}
+
+}  // extern "C"

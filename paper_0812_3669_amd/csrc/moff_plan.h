@@ -1,0 +1,113 @@
+// Host-side plan of the MOFF hot path: geometry, row-band binning, tap groups, launch blocks and workspace
+// layout.  Pure host C++ (no HIP calls), so it also runs in processes without a GPU.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "moff.h"
+
+namespace moff {
+
+constexpr int kThreads = 256;         // threads per workgroup of every hot-path kernel
+constexpr int kWaves = kThreads / 64;  // wavefronts per workgroup (64-wide on CDNA)
+constexpr int kGroupLanes = 64;       // taps per scatter group (one wavefront instruction)
+constexpr uint32_t kEmptyTap = 0xFFFFFFFFu;
+
+// One grid row band of one channel that the footprints touch.  The fused row pass runs one workgroup per
+// (band, time group); inside it wavefront w owns the band rows r with (r - row0) % kWaves == w.
+struct Band {
+  int32_t chan;
+  int32_t row0;         // first grid row of the band
+  int32_t rows;         // band height (<= band_rows of the channel)
+  int32_t r_lo, r_hi;   // rows [r_lo, r_hi] of the band that any footprint touches (absolute)
+  int64_t grp_off[kWaves];  // first tap group of each wavefront (index into the group arrays)
+  int32_t grp_cnt[kWaves];
+};
+
+struct Chan {
+  int32_t n;            // grid size
+  int64_t pix_off;      // sum of n^2 over earlier channels
+  int32_t band_rows;    // rows per band
+  int32_t jmin, jmax;   // rows touched by any footprint
+  int32_t band_first;   // first Band index of this channel
+  int32_t band_count;
+  int32_t cols;         // columns per column-pass workgroup
+  int32_t col_groups;   // n / cols
+};
+
+// A launch block of the fused path: consecutive channels with the same grid size.
+struct Block {
+  int32_t c0, c1;       // channels [c0, c1)
+  int32_t n;
+};
+
+struct Plan {
+  // description (copied)
+  int32_t n_ant = 0, n_pol = 0, n_chan = 0, ksize = 0;
+  double cell_lambda = 1.0;
+  int32_t fft_mode = 0, acc_mode = 0, time_block = 0, volt_format = 0;
+  std::vector<double> ant_xy, freq;
+
+  // geometry
+  std::vector<Chan> chans;
+  std::vector<int32_t> origin;          // [C][A][2] (j0, i0)
+  std::vector<Band> bands;
+  std::vector<int32_t> band_ptr;        // [n_bands + 1] into band_ant
+  std::vector<int32_t> band_ant;        // antennas of each band, ascending
+  // tap groups: meta = (antenna << 16) | cell offset in the band grid ((r - row0) * n + i); kidx = a*K*K + y*K + x
+  std::vector<uint32_t> grp_meta;       // [G][64]
+  std::vector<int32_t> grp_kidx;        // [G][64]
+  std::vector<int32_t> grp_chan;        // [G] channel of each group
+  int64_t n_groups = 0;
+
+  std::vector<Block> blocks;
+  int32_t chans_per_block = 16;
+  int32_t t_block = 16;                 // samples per fused launch block
+  int32_t t_group = 4;                  // samples per row-pass workgroup
+  int64_t pix_total = 0;                // sum of n_c^2
+
+  // workspace layout (byte offsets)
+  size_t ws_twiddle = 0;                // float2 tables, one per distinct n, each n entries
+  std::vector<int32_t> tw_sizes;        // distinct n values in the order of the tables
+  std::vector<size_t> tw_off;           // byte offset of each table
+  size_t ws_bands = 0;                  // Band array (device copy)
+  size_t ws_chans = 0;                  // Chan array (device copy)
+  size_t ws_meta = 0, ws_kidx = 0, ws_gchan = 0, ws_wk = 0;  // tap groups; packed kernels float2 [G][P][64]
+  size_t ws_h = 0, ws_h_bytes = 0;      // row-pass output of one launch block
+  size_t ws_total = 0;
+
+  // binding state
+  void *d_ws = nullptr;
+  bool bound = false, kernels_set = false;
+
+  // kernel timing (moff_profile): events are hipEvent_t stored as void*
+  struct ProfRec {
+    int kind;
+    int64_t cs;
+    void *ev0, *ev1;
+  };
+  bool profiling = false;
+  std::vector<ProfRec> prof;
+  std::vector<void *> ev_pool;
+  size_t ev_used = 0;
+
+  int n_prod() const { return n_pol == 2 ? 4 : 1; }
+  int acc_reals() const { return n_pol == 2 ? 4 : 1; }
+  size_t acc_elem_bytes() const { return acc_mode == MOFF_ACC_FP64_COMP ? 16 : 4; }
+  size_t volt_sample_bytes() const {  // one time sample, all channels
+    return (size_t)n_chan * n_ant * n_pol * (volt_format == MOFF_VOLT_INT8 ? 2 : 8);
+  }
+};
+
+// Builds the plan; on error returns a status and sets *err.
+moff_status build_plan(const moff_plan_desc &d, Plan &p, std::string *err);
+
+// True if this build has an FFT pipeline for grid size n.
+bool fft_size_supported(int n);
+int band_rows_for(int n, int P);
+int cols_for(int n);
+int smallest_supported_size(int need);
+
+}  // namespace moff

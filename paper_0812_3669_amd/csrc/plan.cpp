@@ -1,0 +1,255 @@
+// Host plan: geometry, row-band binning and tap groups of the gridding step (Eq. m6 step 2), launch blocks and
+// the device workspace layout.  No HIP calls here.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "moff_plan.h"
+
+namespace moff {
+
+namespace {
+constexpr double kCLight = 299792458.0;
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+moff_status fail(std::string *err, moff_status s, const std::string &msg) {
+  if (err) *err = msg;
+  return s;
+}
+}  // namespace
+
+// Grid sizes with an FFT pipeline: 2^a * {1, 3, 5}, multiples of 32, up to 512.
+bool fft_size_supported(int n) {
+  static const int ok[] = {32, 64, 96, 128, 160, 192, 256, 320, 384, 512};
+  for (int v : ok)
+    if (v == n) return true;
+  return false;
+}
+
+// Rows per band of the row pass: the band grid (P x rows x n complex64) stays within 32 KB of LDS.
+int band_rows_for(int n, int P) {
+  int h = 16;
+  while (h > 4 && (size_t)P * h * n * 8 > 32768) h /= 2;
+  return h;
+}
+
+// Columns per workgroup of the column pass: the largest power of two <= max(8, 4096 / n) dividing n.
+int cols_for(int n) {
+  int lim = std::max(8, 4096 / n), w = 1;
+  while (w * 2 <= lim && n % (w * 2) == 0) w *= 2;
+  return w;
+}
+
+int smallest_supported_size(int need) {
+  static const int ok[] = {32, 64, 96, 128, 160, 192, 256, 320, 384, 512};
+  for (int v : ok)
+    if (v >= need) return v;
+  return 0;
+}
+
+moff_status build_plan(const moff_plan_desc &d, Plan &p, std::string *err) {
+  if (d.n_ant < 1 || d.n_ant > 65534) return fail(err, MOFF_E_INVALID, "n_ant must be in [1, 65534]");
+  if (d.n_pol != 1 && d.n_pol != 2) return fail(err, MOFF_E_INVALID, "n_pol must be 1 or 2");
+  if (d.n_chan < 1) return fail(err, MOFF_E_INVALID, "n_chan must be >= 1");
+  if (d.ksize < 2 || d.ksize > 8 || (d.ksize & 1)) return fail(err, MOFF_E_INVALID, "ksize must be even, 2..8");
+  if (!d.ant_xy_m || !d.freq_hz) return fail(err, MOFF_E_INVALID, "ant_xy_m and freq_hz must be non-null");
+  if (!(d.cell_lambda > 0.0) || !std::isfinite(d.cell_lambda))
+    return fail(err, MOFF_E_INVALID, "cell_lambda must be positive");
+  if (d.fft_mode != MOFF_FFT_FP32 && d.fft_mode != MOFF_FFT_SPLIT_FP16 && d.fft_mode != MOFF_FFT_SPLIT_BF16)
+    return fail(err, MOFF_E_INVALID, "unknown fft_mode");
+  if (d.fft_mode != MOFF_FFT_FP32) return fail(err, MOFF_E_UNSUPPORTED, "split FFT modes are not built yet");
+  if (d.acc_mode != MOFF_ACC_FP32 && d.acc_mode != MOFF_ACC_FP64_COMP)
+    return fail(err, MOFF_E_INVALID, "unknown acc_mode");
+  if (d.volt_format != MOFF_VOLT_INT8 && d.volt_format != MOFF_VOLT_C64)
+    return fail(err, MOFF_E_INVALID, "unknown volt_format");
+  if (d.time_block < 0) return fail(err, MOFF_E_INVALID, "time_block must be >= 0");
+
+  p.n_ant = d.n_ant;
+  p.n_pol = d.n_pol;
+  p.n_chan = d.n_chan;
+  p.ksize = d.ksize;
+  p.cell_lambda = d.cell_lambda;
+  p.fft_mode = d.fft_mode;
+  p.acc_mode = d.acc_mode;
+  p.volt_format = d.volt_format;
+  p.ant_xy.assign(d.ant_xy_m, d.ant_xy_m + 2 * (size_t)d.n_ant);
+  p.freq.assign(d.freq_hz, d.freq_hz + d.n_chan);
+  for (double v : p.ant_xy)
+    if (!std::isfinite(v)) return fail(err, MOFF_E_INVALID, "non-finite antenna position");
+  for (double f : p.freq)
+    if (!(f > 0.0) || !std::isfinite(f)) return fail(err, MOFF_E_INVALID, "channel frequencies must be positive");
+
+  const int A = p.n_ant, C = p.n_chan, K = p.ksize, P = p.n_pol;
+  p.t_block = d.time_block > 0 ? d.time_block : 16;
+  p.t_group = std::min(4, p.t_block);
+
+  // ---- per-channel grid size and footprints ------------------------------------------------------------
+  p.chans.assign(C, Chan{});
+  p.origin.assign((size_t)C * A * 2, 0);
+  int64_t pix = 0;
+  for (int c = 0; c < C; ++c) {
+    const double scale = p.freq[c] / kCLight / p.cell_lambda;   // cells per metre
+    double xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300;
+    for (int a = 0; a < A; ++a) {
+      xmin = std::min(xmin, p.ant_xy[2 * a] * scale);
+      xmax = std::max(xmax, p.ant_xy[2 * a] * scale);
+      ymin = std::min(ymin, p.ant_xy[2 * a + 1] * scale);
+      ymax = std::max(ymax, p.ant_xy[2 * a + 1] * scale);
+    }
+    int n = d.grid_n ? d.grid_n[c] : 0;
+    if (n < 0) return fail(err, MOFF_E_INVALID, "grid_n must be >= 0");
+    if (n == 0) {
+      // smallest supported size whose centred grid holds every footprint
+      const double span = 2.0 * std::max(std::max(std::fabs(xmin), std::fabs(xmax)),
+                                          std::max(std::fabs(ymin), std::fabs(ymax)));
+      n = smallest_supported_size((int)std::ceil(span) + K + 2);
+      if (n == 0) return fail(err, MOFF_E_UNSUPPORTED, "array too large for the supported grid sizes");
+    }
+    if (!fft_size_supported(n))
+      return fail(err, MOFF_E_UNSUPPORTED, "grid size " + std::to_string(n) + " has no FFT pipeline");
+    Chan &ch = p.chans[c];
+    ch.n = n;
+    ch.pix_off = pix;
+    pix += (int64_t)n * n;
+    ch.jmin = n;
+    ch.jmax = -1;
+    for (int a = 0; a < A; ++a) {
+      const double X = p.ant_xy[2 * a] * scale + n / 2;
+      const double Y = p.ant_xy[2 * a + 1] * scale + n / 2;
+      const double fx = std::floor(X), fy = std::floor(Y);
+      if (!(fx >= -1e9 && fx <= 1e9 && fy >= -1e9 && fy <= 1e9))
+        return fail(err, MOFF_E_INVALID, "antenna coordinate out of range");
+      const int i0 = (int)fx - K / 2 + 1, j0 = (int)fy - K / 2 + 1;
+      if (i0 < 0 || j0 < 0 || i0 + K > n || j0 + K > n)
+        return fail(err, MOFF_E_INVALID,
+                    "footprint of antenna " + std::to_string(a) + " leaves the " + std::to_string(n) +
+                        "^2 grid of channel " + std::to_string(c));
+      p.origin[((size_t)c * A + a) * 2 + 0] = j0;
+      p.origin[((size_t)c * A + a) * 2 + 1] = i0;
+      ch.jmin = std::min(ch.jmin, j0);
+      ch.jmax = std::max(ch.jmax, j0 + K - 1);
+    }
+    ch.band_rows = band_rows_for(n, P);
+    ch.cols = cols_for(n);
+    ch.col_groups = n / ch.cols;
+  }
+  p.pix_total = pix;
+
+  // ---- row bands, band antenna lists and tap groups ------------------------------------------------------
+  p.bands.clear();
+  p.band_ptr.assign(1, 0);
+  p.band_ant.clear();
+  p.grp_meta.clear();
+  p.grp_kidx.clear();
+  p.grp_chan.clear();
+  std::vector<int32_t> last_used;
+  for (int c = 0; c < C; ++c) {
+    Chan &ch = p.chans[c];
+    const int n = ch.n, h = ch.band_rows;
+    ch.band_first = (int32_t)p.bands.size();
+    const int b_lo = ch.jmin / h, b_hi = ch.jmax / h;
+    for (int b = b_lo; b <= b_hi; ++b) {
+      Band bd{};
+      bd.chan = c;
+      bd.row0 = b * h;
+      bd.rows = std::min(h, n - bd.row0);
+      bd.r_lo = std::max(bd.row0, ch.jmin);
+      bd.r_hi = std::min(bd.row0 + bd.rows - 1, ch.jmax);
+      // antennas whose footprint rows [j0, j0+K-1] meet the band (boundary antennas appear in both bands)
+      for (int a = 0; a < A; ++a) {
+        const int j0 = p.origin[((size_t)c * A + a) * 2];
+        if (j0 <= bd.row0 + bd.rows - 1 && j0 + K - 1 >= bd.row0) p.band_ant.push_back(a);
+      }
+      const int32_t lo = p.band_ptr.back(), hi = (int32_t)p.band_ant.size();
+      p.band_ptr.push_back(hi);
+      // tap groups per wavefront: first fit into groups of 64 distinct cells, antennas ascending, so every cell
+      // receives its contributions in ascending antenna order (deterministic sums, no atomics)
+      for (int w = 0; w < kWaves; ++w) {
+        const int64_t g0 = p.n_groups;
+        last_used.assign((size_t)bd.rows * n, -1);
+        std::vector<int32_t> count;
+        int64_t first_open = 0;
+        for (int e = lo; e < hi; ++e) {
+          const int a = p.band_ant[e];
+          const int j0 = p.origin[((size_t)c * A + a) * 2], i0 = p.origin[((size_t)c * A + a) * 2 + 1];
+          for (int y = 0; y < K; ++y) {
+            const int r = j0 + y - bd.row0;
+            if (r < 0 || r >= bd.rows || (r % kWaves) != w) continue;
+            for (int x = 0; x < K; ++x) {
+              const int cell = r * n + i0 + x;
+              int64_t g = std::max<int64_t>(first_open, (int64_t)last_used[cell] + 1);
+              while (g < (int64_t)count.size() && count[g] == kGroupLanes) ++g;
+              if (g == (int64_t)count.size()) {
+                count.push_back(0);
+                p.grp_meta.resize(p.grp_meta.size() + kGroupLanes, kEmptyTap);
+                p.grp_kidx.resize(p.grp_kidx.size() + kGroupLanes, -1);
+                p.grp_chan.push_back(c);
+              }
+              const size_t slot = (size_t)(g0 + g) * kGroupLanes + count[g];
+              p.grp_meta[slot] = ((uint32_t)a << 16) | (uint32_t)cell;
+              p.grp_kidx[slot] = (a * K + y) * K + x;
+              ++count[g];
+              last_used[cell] = (int32_t)g;
+              while (first_open < (int64_t)count.size() && count[first_open] == kGroupLanes) ++first_open;
+            }
+          }
+        }
+        bd.grp_off[w] = g0;
+        bd.grp_cnt[w] = (int32_t)count.size();
+        p.n_groups += (int64_t)count.size();
+      }
+      p.bands.push_back(bd);
+    }
+    ch.band_count = (int32_t)p.bands.size() - ch.band_first;
+  }
+  if ((int64_t)p.bands.size() > INT32_MAX / 2) return fail(err, MOFF_E_UNSUPPORTED, "too many bands");
+
+  // ---- launch blocks of the fused path: consecutive channels with one grid size -----------------------
+  p.blocks.clear();
+  for (int c = 0; c < C;) {
+    Block b{c, c, p.chans[c].n};
+    while (b.c1 < C && p.chans[b.c1].n == b.n && b.c1 - b.c0 < p.chans_per_block) ++b.c1;
+    p.blocks.push_back(b);
+    c = b.c1;
+  }
+
+  // ---- workspace layout -------------------------------------------------------------------------------------
+  size_t off = 0;
+  p.tw_sizes.clear();
+  p.tw_off.clear();
+  for (int c = 0; c < C; ++c)
+    if (std::find(p.tw_sizes.begin(), p.tw_sizes.end(), p.chans[c].n) == p.tw_sizes.end())
+      p.tw_sizes.push_back(p.chans[c].n);
+  p.ws_twiddle = off;
+  for (int n : p.tw_sizes) {
+    p.tw_off.push_back(off);
+    off = align256(off + (size_t)n * 8);
+  }
+  p.ws_bands = off;
+  off = align256(off + p.bands.size() * sizeof(Band));
+  p.ws_chans = off;
+  off = align256(off + p.chans.size() * sizeof(Chan));
+  p.ws_meta = off;
+  off = align256(off + p.grp_meta.size() * 4);
+  p.ws_kidx = off;
+  off = align256(off + p.grp_kidx.size() * 4);
+  p.ws_gchan = off;
+  off = align256(off + p.grp_chan.size() * 4);
+  p.ws_wk = off;
+  off = align256(off + (size_t)p.n_groups * P * kGroupLanes * 8);
+  size_t hmax = 0;
+  for (const Block &b : p.blocks) {
+    size_t s = 0;
+    for (int c = b.c0; c < b.c1; ++c) s += (size_t)P * p.chans[c].n * p.chans[c].n * 8;
+    hmax = std::max(hmax, s * (size_t)p.t_block);
+  }
+  p.ws_h = off;
+  p.ws_h_bytes = hmax;
+  off = align256(off + hmax);
+  p.ws_total = off;
+  return MOFF_OK;
+}
+
+}  // namespace moff

@@ -1,0 +1,229 @@
+"""GPU parity of the HIP path against the FP64 oracle, element by element, through the C ABI.
+
+Tolerance (per image = channel x product): max|gpu - oracle| / max|oracle| <= 1e-5 for XX and YY, and for XY,
+YX the same divided by sqrt(max XX * max YY).  Integer work (voltage unpacking) is bit-exact.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import moff_oracle as ora
+from paper_0812_3669_amd import api, configs, synth
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+DEV = "cuda:0"
+
+
+def _setup(cfg, acc_mode=api.ACC_FP32, time_block=0, chans=None, n_time=None):
+    geo, kern, volts = synth.workload(cfg, n_time=n_time, chans=chans)
+    plan = api.plan_for(cfg, geo, acc_mode=acc_mode, time_block=time_block).bind(DEV)
+    plan.set_kernels(torch.from_numpy(np.ascontiguousarray(kern)).to(DEV))
+    return geo, kern, volts, plan
+
+
+def _run_fused(plan, volts, n_time=None):
+    acc = plan.new_accumulator()
+    v = torch.from_numpy(np.ascontiguousarray(volts)).to(DEV)
+    plan.correlate(v, acc, n_t=n_time)
+    imgs = [im.cpu().numpy().astype(np.complex128) for im in plan.read_image(acc)]
+    torch.cuda.synchronize()
+    return imgs, acc
+
+
+def _check_images(imgs, ref, tol=TOL, label=""):
+    worst = 0.0
+    for c in range(len(ref)):
+        e = ora.relative_errors(imgs[c], ref[c])
+        worst = max(worst, float(e.max()))
+        assert np.all(e <= tol), f"{label} channel {c}: per-product errors {e}"
+    return worst
+
+
+def _small(n, P=2, A=40, C=2, T=9, K=4, seed=0, disk=None, int8=True):
+    disk = disk if disk is not None else 0.6 * n
+    return configs.scaled(configs.PLAIN, index=100 + seed, n_ant=A, n_pol=P, n_chan=C, n_time=T, ksize=K,
+                          grid_n=n, disk_lambda=disk, int8=int8)
+
+
+# ---------------------------------------------------------------------------------------------------------
+# bit-exact integer work
+# ---------------------------------------------------------------------------------------------------------
+def test_unpack_bit_exact():
+    cfg = _small(64, C=3, A=37)
+    geo = synth.geometry(cfg)
+    plan = api.plan_for(cfg, geo).bind(DEV)
+    rng = np.random.default_rng(3)
+    v = rng.integers(-128, 128, size=(cfg.n_chan, cfg.n_ant, 2, 2), dtype=np.int64).astype(np.int8)
+    v[0, 0, 0] = (-128, 127)
+    out = plan.debug_unpack(torch.from_numpy(v).to(DEV)).cpu().numpy()
+    assert np.array_equal(out, v.astype(np.float32))
+
+
+# ---------------------------------------------------------------------------------------------------------
+# staged path: each step against the oracle's step
+# ---------------------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("n,K", [(64, 4), (128, 6), (256, 4)])
+def test_staged_grid(n, K):
+    cfg = _small(n, C=2, A=53, T=5, K=K)
+    geo, kern, volts, plan = _setup(cfg)
+    g = plan.grid(torch.from_numpy(volts).to(DEV))
+    grids = [x.cpu().numpy() for x in plan.split_grids(g, cfg.n_time)]
+    e = ora.unpack(volts)
+    for c in range(cfg.n_chan):
+        origin = ora.footprint_origin(geo.ant_xy_m, geo.freqs_hz[c], cfg.cell_lambda, n, K)
+        for p in range(cfg.n_pol):
+            ref = ora.grid_many(e[:, c, :, p], kern[c, :, p], origin, n)
+            err = np.abs(grids[c][:, p] - ref).max() / np.abs(ref).max()
+            assert err < 1e-6, (c, p, err)
+
+
+@pytest.mark.parametrize("n", [32, 64, 96, 128, 160, 192, 256, 320, 384, 512])
+def test_staged_fft_every_size(n):
+    """moff_fft on oracle-made grids (rounded to complex64) against the oracle's direct DFT."""
+    cfg = _small(n, C=1, A=24, T=2, disk=0.5 * n)
+    geo, kern, volts, plan = _setup(cfg)
+    e = ora.unpack(volts)
+    origin = ora.footprint_origin(geo.ant_xy_m, geo.freqs_hz[0], cfg.cell_lambda, n, cfg.ksize)
+    G = np.stack([ora.grid_many(e[:, 0, :, p], kern[0, :, p], origin, n) for p in range(2)], axis=1)  # [T,P,n,n]
+    G64 = G.astype(np.complex64)
+    buf = torch.from_numpy(np.ascontiguousarray(G64.reshape(-1))).to(DEV)
+    plan.fft(buf, cfg.n_time)
+    ef = plan.split_grids(buf, cfg.n_time)[0].cpu().numpy()                 # FFT pixel order
+    ref = ora.efield_image(G64.astype(np.complex128))                         # centred
+    got = np.fft.fftshift(ef, axes=(-2, -1))
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    assert err < 2e-6, err
+
+
+def test_staged_accumulate_and_readout():
+    n = 64
+    cfg = _small(n, C=2, A=20, T=6)
+    geo, kern, volts, plan = _setup(cfg)
+    rng = np.random.default_rng(1)
+    ef = (rng.standard_normal((cfg.n_time, 2 * plan.pix_total)) +
+          1j * rng.standard_normal((cfg.n_time, 2 * plan.pix_total))).astype(np.complex64)
+    acc = plan.new_accumulator()
+    plan.accumulate(torch.from_numpy(ef.reshape(-1)).to(DEV), cfg.n_time, acc)
+    imgs = [im.cpu().numpy() for im in plan.read_image(acc, n_samples=cfg.n_time, normalize=True)]
+    e128 = ef.astype(np.complex128)
+    for c in range(cfg.n_chan):
+        o = 2 * plan.pix_off[c]
+        ex = np.fft.fftshift(e128[:, o:o + n * n].reshape(-1, n, n), axes=(-2, -1))
+        ey = np.fft.fftshift(e128[:, o + n * n:o + 2 * n * n].reshape(-1, n, n), axes=(-2, -1))
+        ref = np.stack([p.sum(0) for p in ora.pol_products(ex, ey)]) / cfg.n_time
+        assert np.all(ora.relative_errors(imgs[c].astype(np.complex128), ref) < TOL)
+
+
+def test_staged_chain_matches_fused():
+    cfg = _small(128, C=2, A=60, T=7)
+    geo, kern, volts, plan = _setup(cfg)
+    v = torch.from_numpy(volts).to(DEV)
+    g = plan.grid(v)
+    plan.fft(g, cfg.n_time)
+    acc_s = plan.new_accumulator()
+    plan.accumulate(g, cfg.n_time, acc_s)
+    acc_f = plan.new_accumulator()
+    plan.correlate(v, acc_f)
+    a, b = acc_s.cpu().numpy(), acc_f.cpu().numpy()
+    assert np.abs(a - b).max() <= 1e-5 * np.abs(a).max()
+
+
+# ---------------------------------------------------------------------------------------------------------
+# fused path against the whole oracle
+# ---------------------------------------------------------------------------------------------------------
+def test_tiny_workload_full():
+    """64 antennas, 1 channel, 1 pol, complex64 voltages, 64^2 grid, 256 samples: every pixel."""
+    cfg = configs.TINY
+    geo, kern, volts, plan = _setup(cfg)
+    imgs, _ = _run_fused(plan, volts)
+    ref = ora.image(volts, kern, geo.ant_xy_m, geo.freqs_hz, geo.grid_n, cfg.cell_lambda)
+    _check_images(imgs, ref, label="tiny")
+
+
+@pytest.mark.parametrize("n,P,K,A,C,T,int8", [
+    (32, 2, 4, 12, 2, 5, True), (64, 1, 4, 50, 2, 11, True), (96, 2, 4, 30, 1, 3, True),
+    (128, 2, 6, 70, 3, 19, True), (160, 2, 4, 33, 1, 4, True), (192, 1, 8, 41, 1, 5, False),
+    (256, 2, 4, 90, 2, 6, True), (320, 2, 2, 25, 1, 3, True), (384, 2, 6, 44, 1, 3, True),
+    (512, 2, 4, 31, 1, 2, True),
+])
+def test_fused_every_size(n, P, K, A, C, T, int8):
+    cfg = _small(n, P=P, A=A, C=C, T=T, K=K, int8=int8, seed=n)
+    geo, kern, volts, plan = _setup(cfg)
+    imgs, _ = _run_fused(plan, volts)
+    ref = ora.image(volts, kern, geo.ant_xy_m, geo.freqs_hz, geo.grid_n, cfg.cell_lambda)
+    _check_images(imgs, ref, label=f"n={n}")
+
+
+def test_ragged_time_blocks_and_fp64_accumulator():
+    cfg = _small(64, C=3, A=45, T=37)
+    for mode in (api.ACC_FP32, api.ACC_FP64_COMP):
+        geo, kern, volts, plan = _setup(cfg, acc_mode=mode, time_block=8)
+        imgs, _ = _run_fused(plan, volts)
+        ref = ora.image(volts, kern, geo.ant_xy_m, geo.freqs_hz, geo.grid_n, cfg.cell_lambda)
+        _check_images(imgs, ref, label=f"acc mode {mode}")
+
+
+def test_plain_workload_channels():
+    """The plain workload (256 antennas, 32 channels, 128^2, dual pol): all channels through the fused path,
+    lowest and highest channel checked pixel by pixel over the first 512 samples."""
+    cfg = configs.PLAIN
+    geo, kern, volts, plan = _setup(cfg, n_time=512)
+    imgs, _ = _run_fused(plan, volts)
+    sel = [0, cfg.n_chan - 1]
+    ref = ora.image(volts[:, sel], kern[sel], geo.ant_xy_m, geo.freqs_hz[sel], geo.grid_n[sel], cfg.cell_lambda)
+    _check_images([imgs[c] for c in sel], ref, label="plain")
+
+
+# ---------------------------------------------------------------------------------------------------------
+# degenerate cases and properties
+# ---------------------------------------------------------------------------------------------------------
+def test_zero_samples_leave_accumulator_untouched():
+    cfg = _small(64, C=1, A=10, T=3)
+    geo, kern, volts, plan = _setup(cfg)
+    acc = plan.new_accumulator().fill_(3.5)
+    plan.correlate(torch.from_numpy(volts).to(DEV), acc, n_t=0)
+    torch.cuda.synchronize()
+    assert torch.all(acc == 3.5)
+
+
+def test_single_antenna_and_stacked_antennas():
+    n = 64
+    for xy in (np.array([[2.3, -4.1]]), np.tile(np.array([[1.2, 0.7]]), (9, 1))):
+        geo = synth.Geometry(xy, np.array([configs.C_LIGHT]), np.array([n], dtype=np.int32), 1.0, 8)
+        cfg = configs.scaled(configs.PLAIN, n_ant=xy.shape[0], n_chan=1, ksize=8, grid_n=n, n_time=5)
+        rng = np.random.default_rng(2)
+        kern = (rng.standard_normal((1, xy.shape[0], 2, 8, 8)) + 1j * rng.standard_normal((1, xy.shape[0], 2, 8, 8)))
+        kern = kern.astype(np.complex64)
+        volts = rng.integers(-127, 128, size=(5, 1, xy.shape[0], 2, 2)).astype(np.int8)
+        plan = api.plan_for(cfg, geo).bind(DEV)
+        plan.set_kernels(torch.from_numpy(kern).to(DEV))
+        imgs, _ = _run_fused(plan, volts)
+        ref = ora.image(volts, kern, xy, geo.freqs_hz, geo.grid_n, 1.0)
+        _check_images(imgs, ref, label=f"{xy.shape[0]} antennas")
+
+
+def test_deterministic_and_split_integration():
+    """Same input twice -> bit-identical accumulators; an integration split at a time-block boundary equals
+    the unsplit one bit for bit (accumulation is linear in time: checkpoint and resume)."""
+    cfg = _small(128, C=2, A=64, T=32)
+    geo, kern, volts, plan = _setup(cfg, time_block=8)
+    v = torch.from_numpy(volts).to(DEV)
+    a1, a2, a3 = plan.new_accumulator(), plan.new_accumulator(), plan.new_accumulator()
+    plan.correlate(v, a1)
+    plan.correlate(v, a2)
+    plan.correlate(v[:16].contiguous(), a3)
+    plan.correlate(v[16:].contiguous(), a3)
+    torch.cuda.synchronize()
+    assert torch.equal(a1, a2)
+    assert torch.equal(a1, a3)
+
+
+def test_hermitian_products_and_positivity():
+    cfg = _small(64, C=1, A=30, T=8)
+    geo, kern, volts, plan = _setup(cfg)
+    imgs, _ = _run_fused(plan, volts)
+    im = imgs[0]
+    assert np.array_equal(im[3], np.conj(im[2]))
+    assert im[0].real.min() >= 0 and im[1].real.min() >= 0
+    assert np.all(np.abs(im[2]) ** 2 <= im[0].real * im[1].real * (1 + 1e-4) + 1e-3)
