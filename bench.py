@@ -84,8 +84,12 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--acc", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--fft", choices=["fp32", "split_fp16", "split_bf16"], default="fp32",
+                    help="transform arithmetic: plain FP32 (VALU) or split-precision matrix-core DFT-GEMMs")
     ap.add_argument("--time", type=int, default=0, help="samples per step (default: the full 16384)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--autotune", action="store_true", help="tune the launch shape on the first 256 samples")
+    ap.add_argument("--graph", action="store_true", help="replay the correlation from a captured HIP graph")
     ap.add_argument("--calibrate-copy", action="store_true", help="run a 1 GiB device copy (PMC calibration)")
     args = ap.parse_args()
 
@@ -117,21 +121,31 @@ def main():
     kern_np = synth.kernels(geo, g, cfg.n_pol)
     volts = synth.DeviceVoltages(cfg, geo, g, sk, dev, chunk=64).all(T)
     acc_mode = api.ACC_FP64_COMP if args.acc == "fp64" else api.ACC_FP32
-    plan = api.plan_for(cfg, geo, acc_mode=acc_mode).bind(dev)
+    fft_mode = {"fp32": api.FFT_FP32, "split_fp16": api.FFT_SPLIT_FP16, "split_bf16": api.FFT_SPLIT_BF16}[args.fft]
+    plan = api.plan_for(cfg, geo, acc_mode=acc_mode, fft_mode=fft_mode)
+    room = max(plan.workspace_bytes_for(tb, cpb) for tb in (8, 16, 32, 64) for cpb in (4, 8, 16, 32, 64, 128)) \
+        if args.autotune else None
+    plan.bind(dev, workspace_bytes=room)
     plan.set_kernels(torch.from_numpy(kern_np).to(dev))
     acc = plan.new_accumulator()
+    tuned = None
+    if args.autotune:
+        tuned = plan.autotune(volts, acc, n_t=min(T, 256))
+        print(f"bench: autotuned launch shape {tuned}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     print("bench: workload resident; warmup", file=sys.stderr, flush=True)
 
+    run = plan.correlate_graph if args.graph else plan.correlate
+
     def step():
         acc.zero_()
-        plan.correlate(volts, acc, n_t=T)
+        run(volts, acc, n_t=T)
         return plan.read_image(acc, n_samples=T, split=False)
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    plan.profile(True)
+    plan.profile(not args.graph)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record()
@@ -141,6 +155,14 @@ def main():
     torch.cuda.synchronize()
     plan.profile(False)
     ms = e0.elapsed_time(e1) / args.steps
+    if args.graph:
+        # kernel timing needs the eager path (events cannot be recorded inside the replayed graph): one extra,
+        # untimed step with per-launch events
+        plan.profile(True)
+        acc.zero_()
+        plan.correlate(volts, acc, n_t=T)
+        torch.cuda.synchronize()
+        plan.profile(False)
     cs = cfg.n_chan * T
     value = cs / (ms / 1e3)
     print(f"bench: {ms:.2f} ms/step", file=sys.stderr, flush=True)
@@ -165,13 +187,18 @@ def main():
                 "kernel_share": {names[k]: kt[k]["ms"] / (kt[0]["ms"] + kt[1]["ms"]) for k in kt}}
 
     out = {
-        "metric": "channel-samples imaged/s (N=2048, 256^2 grid), plain FP32 path",
+        "metric": "channel-samples imaged/s (N=2048, 256^2 grid), " +
+                  ("plain FP32 path" if args.fft == "fp32" else f"{args.fft} matrix-core transform"),
         "value": value, "unit": "channel-samples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp32": "f32", "split_fp16": "f16x2->f32", "split_bf16": "bf16x3->f32"}[args.fft],
         "data": "synthetic (seeded point sources + noise, int8 voltages)",
         "config": {"workload": "headline: 2048 antennas, 200-lambda disk, 128 channels 100-130 MHz, 2 pols, "
                                "4x4 kernels, 256^2 grid, 16384 samples, int8",
                    "channel_samples_per_step": cs, "accumulator": args.acc,
+                   "fft": args.fft,
+                   "launch_shape": dict(zip(("time_block", "chans_per_block", "time_group"), plan.launch_shape())),
+                   "graph_replay": bool(args.graph),
                    "algorithmic_flops_per_cs": cfg.flops_per_cs(),
                    "achieved_algorithmic_tflops": value * cfg.flops_per_cs() / 1e12},
         "roofline": roofline,

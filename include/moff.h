@@ -33,9 +33,10 @@
  *   kernels     float [C][A][P][K][K][2] (complex64), the weight N~ already folded in
  *   grid/efield float [n_t][sum_c P n_c^2][2]: per sample, channel c's block starts at P * pix_off(c), pol p at
  *               + p n_c^2, row-major [j][i].  E-field images are in FFT order: index k <-> pixel (k + n/2) mod n.
- *   accumulator float (MOFF_ACC_FP32) or double pairs (sum, carry) (MOFF_ACC_FP64_COMP) [sum_c R n_c^2], with R = 4
- *               reals per pixel (XX, YY, Re XY, Im XY) for P = 2 and R = 1 for P = 1, channel c at R * pix_off(c),
- *               pixels in FFT order.  Zero it before the first call (any fill kernel); calls add to it.
+ *   accumulator float (MOFF_ACC_FP32) or double pairs (sum, carry) (MOFF_ACC_FP64_COMP), R reals per pixel:
+ *               R = 4 (XX, YY, Re XY, Im XY) for P = 2, R = 1 for P = 1.  Channel c starts at R * pix_off(c); its
+ *               layout is internal (column-group tiles matching the column pass), so read it with
+ *               moff_read_image.  Zero it before the first call (any fill kernel); calls add to it.
  *   image       float [sum_c M n_c^2][2] (complex64), M = 4 products XX, YY, XY, YX (M = 1 for P = 1), channel c at
  *               M * pix_off(c), product-major, pixels centred (row q = m, column p = l).
  *   pix_off(c) = sum_{c' < c} n_c'^2  (moff_chan_offset).
@@ -76,8 +77,10 @@ typedef struct {
   double cell_lambda;       /* grid cell size in wavelengths (> 0) */
   int32_t fft_mode;         /* moff_fft_mode */
   int32_t acc_mode;         /* moff_acc_mode */
-  int32_t time_block;       /* samples per fused launch block (0 = library default) */
+  int32_t time_block;       /* samples per fused launch block (0 = library default, 16) */
   int32_t volt_format;      /* moff_volt_format */
+  int32_t chans_per_block;  /* channels per fused launch block (0 = library default, 16) */
+  int32_t time_group;       /* samples per row-pass workgroup (0 = library default, 4) */
 } moff_plan_desc;
 
 /* Host only.  Validates the description, computes every antenna's footprint per channel, bins antennas into
@@ -132,6 +135,27 @@ moff_status moff_debug_unpack(moff_plan_t plan, const void *d_volt, float *d_out
 moff_status moff_debug_tile_counts(moff_plan_t plan, int64_t *n_band_total, int64_t *n_entries,
                                    int32_t *band_rows);
 moff_status moff_debug_tiles(moff_plan_t plan, int32_t *h_origin, int32_t *h_band_ptr, int32_t *h_band_ant);
+
+/* Launch shape of the fused path: samples per launch block, channels per launch block (consecutive channels
+ * with one grid size) and samples per row-pass workgroup.  moff_workspace_size_for gives the workspace a shape
+ * needs; moff_set_launch_shape applies one to a bound plan (MOFF_E_BUDGET if the bound workspace is too small;
+ * nothing changes then).  The shape changes speed only, never results beyond FP32 summation order. */
+moff_status moff_workspace_size_for(moff_plan_t plan, int32_t time_block, int32_t chans_per_block, size_t *bytes);
+moff_status moff_set_launch_shape(moff_plan_t plan, int32_t time_block, int32_t chans_per_block, int32_t time_group);
+moff_status moff_get_launch_shape(moff_plan_t plan, int32_t *time_block, int32_t *chans_per_block,
+                                  int32_t *time_group);
+
+/* Autotuner.  Times moff_correlate of n_t samples of d_volt for candidate launch shapes that fit the bound
+ * workspace (d_acc is used as scratch and left holding garbage), keeps the fastest and returns it with its time
+ * per call in ms.  Blocks the calling host thread (it synchronises the stream). */
+moff_status moff_autotune(moff_plan_t plan, const void *d_volt, int64_t n_t, void *d_acc, void *stream,
+                          int32_t *time_block, int32_t *chans_per_block, int32_t *time_group, double *best_ms);
+
+/* Fused path replayed from a HIP graph.  The first call for a given (d_volt, n_t, d_acc) records every launch
+ * moff_correlate would make (on an internal capture stream) into a graph and instantiates it; every call then
+ * launches that graph on the caller's stream, one host call per integration.  Changing the launch shape or
+ * rebinding drops the cached graphs.  The buffers' contents may change between calls; their addresses may not. */
+moff_status moff_correlate_graph(moff_plan_t plan, const void *d_volt, int64_t n_t, void *d_acc, void *stream);
 
 /* Kernel timing (tracing).  moff_profile(plan, 1) starts recording a pair of HIP events around every launch of
  * the fused path on the caller's stream (earlier records are dropped); moff_profile(plan, 0) stops.  After the

@@ -21,6 +21,7 @@ class PlanDesc(C.Structure):
         ("ant_xy_m", C.POINTER(C.c_double)), ("freq_hz", C.POINTER(C.c_double)),
         ("grid_n", C.POINTER(C.c_int32)), ("cell_lambda", C.c_double),
         ("fft_mode", C.c_int32), ("acc_mode", C.c_int32), ("time_block", C.c_int32), ("volt_format", C.c_int32),
+        ("chans_per_block", C.c_int32), ("time_group", C.c_int32),
     ]
 
 
@@ -42,6 +43,12 @@ _SIGS = {
     "moff_debug_unpack": ([_P, _P, _P, _P], C.c_int),
     "moff_debug_tile_counts": ([_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int32)], C.c_int),
     "moff_debug_tiles": ([_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),
+    "moff_workspace_size_for": ([_P, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)], C.c_int),
+    "moff_set_launch_shape": ([_P, C.c_int32, C.c_int32, C.c_int32], C.c_int),
+    "moff_get_launch_shape": ([_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),
+    "moff_autotune": ([_P, _P, C.c_int64, _P, _P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                       C.POINTER(C.c_double)], C.c_int),
+    "moff_correlate_graph": ([_P, _P, C.c_int64, _P, _P], C.c_int),
     "moff_profile": ([_P, C.c_int32], C.c_int),
     "moff_profile_read": ([_P, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_int64)],
                           C.c_int),

@@ -15,7 +15,8 @@ from typing import List, Optional, Sequence
 import numpy as np
 
 from . import _lib
-from ._lib import ACC_FP32, ACC_FP64_COMP, FFT_FP32, VOLT_C64, VOLT_INT8  # noqa: F401
+from ._lib import (ACC_FP32, ACC_FP64_COMP, FFT_FP32, FFT_SPLIT_BF16, FFT_SPLIT_FP16,  # noqa: F401
+                   VOLT_C64, VOLT_INT8)
 
 
 class MoffError(RuntimeError):
@@ -47,7 +48,7 @@ class Plan:
 
     def __init__(self, ant_xy_m, freqs_hz, grid_n=None, n_pol: int = 2, ksize: int = 4, cell_lambda: float = 1.0,
                  fft_mode: int = FFT_FP32, acc_mode: int = ACC_FP32, time_block: int = 0,
-                 volt_format: int = VOLT_INT8):
+                 volt_format: int = VOLT_INT8, chans_per_block: int = 0, time_group: int = 0):
         self.lib = _lib.load()
         xy = np.ascontiguousarray(ant_xy_m, dtype=np.float64)
         fr = np.ascontiguousarray(freqs_hz, dtype=np.float64)
@@ -63,6 +64,7 @@ class Plan:
         d.grid_n = gn.ctypes.data_as(C.POINTER(C.c_int32)) if gn is not None else None
         d.cell_lambda = cell_lambda
         d.fft_mode, d.acc_mode, d.time_block, d.volt_format = fft_mode, acc_mode, time_block, volt_format
+        d.chans_per_block, d.time_group = chans_per_block, time_group
         h = C.c_void_p()
         _check(self.lib.moff_plan(C.byref(d), C.byref(h)), "moff_plan")
         self._h = h
@@ -105,9 +107,16 @@ class Plan:
         return self._size(self.lib.moff_image_size)
 
     # ---- device state --------------------------------------------------------------------------------------------
-    def bind(self, device="cuda", stream=None):
+    def workspace_bytes_for(self, time_block: int, chans_per_block: int) -> int:
+        b = C.c_size_t()
+        _check(self.lib.moff_workspace_size_for(self._h, time_block, chans_per_block, C.byref(b)),
+               "moff_workspace_size_for")
+        return b.value
+
+    def bind(self, device="cuda", stream=None, workspace_bytes: Optional[int] = None):
+        """Allocates the device workspace (at least ``workspace_bytes``, e.g. room for the autotuner) and binds."""
         import torch
-        n = max(self.workspace_bytes, 256)
+        n = max(self.workspace_bytes, workspace_bytes or 0, 256)
         self._ws = torch.empty(n + 256, dtype=torch.uint8, device=device)
         base = self._ws.data_ptr()
         aligned = (base + 255) & ~255
@@ -147,6 +156,30 @@ class Plan:
         self._check_volts(volts, n_t)
         _check(self.lib.moff_correlate(self._h, _ptr(volts), n_t, _ptr(acc), _stream_handle(stream)),
                "moff_correlate")
+
+    def correlate_graph(self, volts, acc, n_t: Optional[int] = None, stream=None):
+        """Same as correlate, replayed from a captured HIP graph (captured on first use per buffer set)."""
+        n_t = volts.shape[0] if n_t is None else n_t
+        self._check_volts(volts, n_t)
+        _check(self.lib.moff_correlate_graph(self._h, _ptr(volts), n_t, _ptr(acc), _stream_handle(stream)),
+               "moff_correlate_graph")
+
+    def launch_shape(self):
+        tb, cpb, tg = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(self.lib.moff_get_launch_shape(self._h, C.byref(tb), C.byref(cpb), C.byref(tg)), "launch shape")
+        return tb.value, cpb.value, tg.value
+
+    def set_launch_shape(self, time_block: int, chans_per_block: int, time_group: int):
+        _check(self.lib.moff_set_launch_shape(self._h, time_block, chans_per_block, time_group), "set launch shape")
+
+    def autotune(self, volts, acc, n_t: Optional[int] = None, stream=None):
+        """Times candidate launch shapes on this input (acc is scratch); keeps and returns the fastest."""
+        n_t = volts.shape[0] if n_t is None else n_t
+        self._check_volts(volts, n_t)
+        tb, cpb, tg, ms = C.c_int32(), C.c_int32(), C.c_int32(), C.c_double()
+        _check(self.lib.moff_autotune(self._h, _ptr(volts), n_t, _ptr(acc), _stream_handle(stream), C.byref(tb),
+                                      C.byref(cpb), C.byref(tg), C.byref(ms)), "moff_autotune")
+        return {"time_block": tb.value, "chans_per_block": cpb.value, "time_group": tg.value, "ms": ms.value}
 
     def grid(self, volts, n_t: Optional[int] = None, out=None, stream=None):
         import torch

@@ -19,6 +19,14 @@ constexpr int band_rows_ce(int n, int P) {
   return h;
 }
 
+// Columns per column-pass workgroup (must match cols_for in the plan): the largest power of two
+// <= max(8, 2048 / n) dividing n.
+constexpr int cols_ce(int n) {
+  int lim = 2048 / n > 8 ? 2048 / n : 8, w = 1;
+  while (w * 2 <= lim && n % (w * 2) == 0) w *= 2;
+  return w;
+}
+
 struct RowArgs {
   const Band *bands;
   const Chan *chans;
@@ -34,6 +42,7 @@ struct RowArgs {
   const float2 *tw;
   float2 *io;                // fused: H of the launch block; staged: grid buffer
   int64_t sample_stride;     // staged grid: float2 per sample (P * sum n_c^2)
+  int n_chan_block;          // fused: channels in the launch block (XCD-aware workgroup mapping)
 };
 
 struct ColArgs {
@@ -45,7 +54,65 @@ struct ColArgs {
   float2 *out;               // staged: grid buffer (in place)
   void *acc;                 // fused: accumulator
   int64_t sample_stride;
+  int n_chan_block;          // fused: channels in the launch block (XCD-aware workgroup mapping)
 };
+
+// XCD-aware workgroup mapping of the fused passes.  Workgroups are dispatched round-robin over the 8 XCDs
+// (workgroup b runs on XCD b % 8), so channel c0 + k of a launch block is given to XCD k % 8: its tap tables and
+// voltages stay in one XCD's L2 instead of being fetched by all eight.  Padding workgroups get false.
+constexpr int kXcds = 8;
+
+__device__ inline bool rows_xcd_map(const RowArgs &a, int &band, int &tg) {
+  const int x = (int)(blockIdx.x % kXcds), s = (int)(blockIdx.x / kXcds);
+  const int tgroups = (a.nt + a.t_group - 1) / a.t_group;
+  tg = s % tgroups;
+  int slot = s / tgroups;
+  for (int k = x; k < a.n_chan_block; k += kXcds) {
+    const Chan &ch = a.chans[a.c0 + k];
+    if (slot < ch.band_count) {
+      band = ch.band_first + slot;
+      return true;
+    }
+    slot -= ch.band_count;
+  }
+  return false;
+}
+
+__device__ inline bool cols_xcd_map(const ColArgs &a, int groups, int &c, int &g) {
+  const int x = (int)(blockIdx.x % kXcds), s = (int)(blockIdx.x / kXcds);
+  const int k = x + kXcds * (s / groups);
+  if (k >= a.n_chan_block) return false;
+  c = a.c0 + k;
+  g = s % groups;
+  return true;
+}
+
+// Workgroups of the fused passes for a launch block (host side, same mapping as above).
+inline int rows_xcd_grid(const Plan &p, const Block &b, int tgroups) {
+  int mx = 0;
+  for (int x = 0; x < kXcds; ++x) {
+    int n = 0;
+    for (int k = x; k < b.c1 - b.c0; k += kXcds) n += p.chans[b.c0 + k].band_count;
+    mx = n > mx ? n : mx;
+  }
+  return kXcds * tgroups * mx;
+}
+
+inline int cols_xcd_grid(const Block &b, int groups) {
+  return kXcds * groups * ((b.c1 - b.c0 + kXcds - 1) / kXcds);
+}
+
+typedef float vfloat2 __attribute__((ext_vector_type(2)));
+
+// Streaming store / load of the row-transform buffer: written once, read once, kept out of the way of the
+// tap tables in L2.
+__device__ __forceinline__ void store_stream(float2 *p, float2 v) {
+  __builtin_nontemporal_store(vfloat2{v.x, v.y}, reinterpret_cast<vfloat2 *>(p));
+}
+__device__ __forceinline__ float2 load_stream(const float2 *p) {
+  const vfloat2 v = __builtin_nontemporal_load(reinterpret_cast<const vfloat2 *>(p));
+  return make_float2(v.x, v.y);
+}
 
 struct AccArgs {
   const Chan *chans;
@@ -81,5 +148,14 @@ hipError_t launch_pack_kernels(const float2 *kern, const int32_t *kidx, const in
                                int64_t n_groups, int A, int P, int KK, hipStream_t st);
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t st);
 hipError_t launch_unpack_debug(const void *volt, int fmt, float2 *out, int64_t count, hipStream_t st);
+hipError_t set_lds_limit_ext(const void *fn);
+
+// precision form (256^2 grids, two pols; kernels_mfma.hip)
+constexpr size_t kMfmaTableBytes = (size_t)17 * 2 * 3 * 64 * 8 * 2;
+size_t rows_mfma_lds_bytes();
+size_t cols_mfma_lds_bytes();
+hipError_t launch_mfma_table(uint16_t *tab, int bf16, hipStream_t st);
+hipError_t launch_rows_mfma(int bf16, const RowArgs &a, const uint16_t *table, int grid, hipStream_t st);
+hipError_t launch_cols_mfma(int bf16, int accm, const ColArgs &a, const uint16_t *table, int grid, hipStream_t st);
 
 }  // namespace moff

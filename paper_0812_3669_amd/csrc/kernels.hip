@@ -24,6 +24,7 @@
 #include <utility>
 
 #include "fft_radix.h"
+#include "fft_sizes.h"
 #include "kernels.h"
 
 namespace moff {
@@ -32,12 +33,28 @@ namespace moff {
 // Utility kernels
 // ------------------------------------------------------------------------------------------------------------
 
-// Twiddle table tw[e] = exp(+2 pi i e / n), generated in FP64 from the exact rational angle and rounded once.
-__global__ void k_twiddle_f64(float2 *tw, int n) {
+// Twiddle tables of one transform length, generated in FP64 from exact rational angles and rounded once.
+// Stage s > 0 (radix R, span L) multiplies input m of butterfly j by w_{L R}^{(j mod L) m}; its table is laid out
+// [m][k] (k = j mod L) so that lanes with consecutive k read consecutive LDS words.  Table of the second stage
+// (R1 x L1 = R0 R1 entries) first, then that of the third stage (R2 x L2 = n entries) if there is one.
+__global__ void k_twiddle_f64(float2 *tw, int n, int r0, int r1, int r2) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n) return;
+  const int s1 = r0 * r1;
+  const int total = s1 + (r2 > 1 ? n : 0);
+  if (e >= total) return;
+  int span, k, m;
+  if (e < s1) {
+    span = s1;
+    m = e / r0;
+    k = e - m * r0;
+  } else {
+    span = n;
+    m = (e - s1) / s1;
+    k = (e - s1) - m * s1;
+  }
+  const long long km = (long long)k * m % span;   // exact angle reduction in integers
   double s, c;
-  sincospi(2.0 * (double)e / (double)n, &s, &c);
+  sincospi(2.0 * (double)km / (double)span, &s, &c);
   tw[e] = make_float2((float)c, (float)s);
 }
 
@@ -85,13 +102,15 @@ __global__ void k_unpack_debug(const void *volt, int fmt, float2 *out, int64_t c
 // (j / L) L R + (j mod L) + r L.  Between stages the outputs live in LDS in a padded [r][j] layout (row stride
 // NB + 1) so that both the writes (consecutive j) and the next stage's reads avoid bank conflicts.
 // ------------------------------------------------------------------------------------------------------------
+// tw: the twiddle tables of the transform length (see k_twiddle_f64); stage with span L uses the table at
+// offset 0 when L is the first radix and at offset R0 R1 otherwise.
 template <int N, int R, int L>
 __device__ __forceinline__ void twiddle_dft(float2 (&x)[R], int j, const float2 *__restrict__ tw) {
   if constexpr (L > 1) {
     const int k = j % L;
-    constexpr int TS = N / (L * R);
+    constexpr int OFF = L == Fac<N>::R0 ? 0 : Fac<N>::R0 * Fac<N>::R1;
 #pragma unroll
-    for (int m = 1; m < R; ++m) x[m] = cmul(x[m], tw[k * m * TS]);
+    for (int m = 1; m < R; ++m) x[m] = cmul(x[m], tw[OFF + m * L + k]);
   }
   dft<R>(x);
 }
@@ -167,7 +186,7 @@ __device__ __forceinline__ void row_stage_lds(float2 *buf, int ntr, const float2
   __syncthreads();
 }
 
-// Last stage: LDS -> global rows (natural order).
+// Last stage: LDS -> global; dst(tr, q, value) stores output q of transform tr.
 template <int N, int R, int L, int RP, int LP, int MAXB, class Base, class Dst>
 __device__ __forceinline__ void row_stage_out(const float2 *buf, int ntr, const float2 *tw, Base tr_base, Dst dst) {
   constexpr int NB = N / R;
@@ -182,9 +201,32 @@ __device__ __forceinline__ void row_stage_out(const float2 *buf, int ntr, const 
 #pragma unroll
       for (int m = 0; m < R; ++m) x[m] = in[lds_addr<N, RP, LP>(j + m * NB)];
       twiddle_dft<N, R, L>(x, j, tw);
-      float2 *o = dst(tr);
 #pragma unroll
-      for (int r = 0; r < R; ++r) o[nat_out<N, R, L>(j, r)] = x[r];
+      for (int r = 0; r < R; ++r) dst(tr, nat_out<N, R, L>(j, r), x[r]);
+    }
+  }
+}
+
+// Voltage of antenna `ant` (both pols) for one (t, c) row, read straight from global memory (L1/L2 hits:
+// the row is 2 P bytes per antenna and every band of the channel touches it).
+template <int P>
+__device__ __forceinline__ void load_volt(const void *row, int fmt, int ant, float2 (&e)[P]) {
+  if (fmt == 0) {
+    if constexpr (P == 2) {
+      const uint32_t v = reinterpret_cast<const uint32_t *>(row)[ant];
+      e[0] = make_float2((float)(int8_t)(v & 0xFF), (float)(int8_t)((v >> 8) & 0xFF));
+      e[1] = make_float2((float)(int8_t)((v >> 16) & 0xFF), (float)(int8_t)(v >> 24));
+    } else {
+      const uint16_t v = reinterpret_cast<const uint16_t *>(row)[ant];
+      e[0] = make_float2((float)(int8_t)(v & 0xFF), (float)(int8_t)(v >> 8));
+    }
+  } else {
+    if constexpr (P == 2) {
+      const float4 v = reinterpret_cast<const float4 *>(row)[ant];
+      e[0] = make_float2(v.x, v.y);
+      e[1] = make_float2(v.z, v.w);
+    } else {
+      e[0] = reinterpret_cast<const float2 *>(row)[ant];
     }
   }
 }
@@ -192,67 +234,90 @@ __device__ __forceinline__ void row_stage_out(const float2 *buf, int ntr, const 
 template <int N, int P, int MODE>
 __global__ __launch_bounds__(kThreads) void k_rows(RowArgs a) {
   using PP = Pipe<N>;
-  constexpr int TS = PP::TS;
+  constexpr int TS = row_stride(N);   // even: rows start on 16-byte boundaries
+  static_assert(TS >= N + PP::RMAX - 1, "row stride too small for the padded layout");
   constexpr int HB = band_rows_ce(N, P);             // rows per band
+  constexpr int GCH = 8;                             // tap groups whose loads are issued together
   extern __shared__ float4 smem4[];
-  const int hb = HB;
-  float2 *grid = reinterpret_cast<float2 *>(smem4);  // [P][hb][TS]
-  float2 *tws = grid + P * hb * TS;                  // [N]
-  void *vs = tws + N;                                // staged voltages of one sample, [A][P]
+  float2 *grid = reinterpret_cast<float2 *>(smem4);  // [P][HB][TS]
+  float2 *tws = grid + P * HB * TS;                  // [2N] twiddle tables
 
-  const int nb = a.n_bands;
-  const Band bd = a.bands[a.band_begin + (int)(blockIdx.x % nb)];
-  const int tg = (int)(blockIdx.x / nb);
+  int band, tg;
+  if constexpr (MODE == ROW_FUSED) {
+    if (!rows_xcd_map(a, band, tg)) return;
+  } else {
+    band = a.band_begin + (int)(blockIdx.x % a.n_bands);
+    tg = (int)(blockIdx.x / a.n_bands);
+  }
+  const Band *bp = a.bands + band;
+  struct {
+    int chan, row0, r_lo, r_hi;
+  } bd = {bp->chan, bp->row0, bp->r_lo, bp->r_hi};
   const int c = bd.chan;
   const int t_lo = a.t0 + tg * a.t_group;
   const int t_hi = min(a.t0 + a.nt, t_lo + a.t_group);
   const int nrow = bd.r_hi - bd.r_lo + 1;
   const int ntr = P * nrow;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t g0 = bp->grp_off[wave];
+  const int gc = bp->grp_cnt[wave];
+  const size_t vbytes = (size_t)a.n_ant * P * (a.volt_fmt == 0 ? 2 : 8);   // one (t, c) voltage row
 
-  for (int i = threadIdx.x; i < N; i += kThreads) tws[i] = a.tw[i];
+  for (int i = threadIdx.x; i < 2 * N; i += kThreads) tws[i] = a.tw[i];
 
+  // transform tr = p * nrow + r (pol p, touched row r); P <= 2, so no division
+  auto tr_pol = [&](int tr) { return (P == 2 && tr >= nrow) ? 1 : 0; };
   auto tr_base = [&](int tr) {
-    const int p = tr / nrow, r = tr - p * nrow;
-    return (p * hb + (bd.r_lo - bd.row0 + r)) * TS;
+    const int p = tr_pol(tr), r = tr - p * nrow;
+    return (p * HB + (bd.r_lo - bd.row0 + r)) * TS;
   };
 
   for (int t = t_lo; t < t_hi; ++t) {
     if constexpr (MODE == ROW_FUSED || MODE == ROW_GRID) {
-      // stage this sample's voltage row of channel c and clear the band grid
-      const int64_t row = ((int64_t)t * a.n_chan + c) * a.n_ant * P;
-      if (a.volt_fmt == 0) {
-        const uint16_t *src = reinterpret_cast<const uint16_t *>(a.volt) + row;
-        uint16_t *dst = reinterpret_cast<uint16_t *>(vs);
-        for (int i = threadIdx.x; i < a.n_ant * P; i += kThreads) dst[i] = src[i];
-      } else {
-        const float2 *src = reinterpret_cast<const float2 *>(a.volt) + row;
-        float2 *dst = reinterpret_cast<float2 *>(vs);
-        for (int i = threadIdx.x; i < a.n_ant * P; i += kThreads) dst[i] = src[i];
+      // clear the band grid (16-byte stores over the whole contiguous region)
+      {
+        float4 *g4 = reinterpret_cast<float4 *>(grid);
+#pragma unroll 4
+        for (int i = threadIdx.x; i < P * HB * TS / 2; i += kThreads) g4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
       }
-      for (int i = threadIdx.x; i < P * hb * TS; i += kThreads) grid[i] = make_float2(0.f, 0.f);
       __syncthreads();
-      // deterministic scatter: this wavefront's tap groups, one tap per lane, distinct cells per group
-      const int64_t g0 = bd.grp_off[wave];
-      const int gc = bd.grp_cnt[wave];
-      for (int g = 0; g < gc; ++g) {
-        const uint32_t m = a.meta[(g0 + g) * 64 + lane];
-        if (m != kEmptyTap) {
-          const int ant = (int)(m >> 16), cell = (int)(m & 0xFFFFu);
-          const int rr = cell / N, col = cell - rr * N;
+      // deterministic scatter: this wavefront's tap groups, one tap per lane, 64 distinct cells per group;
+      // the loads of GCH groups are issued before any of them is used
+      const char *vrow = reinterpret_cast<const char *>(a.volt) + ((int64_t)t * a.n_chan + c) * vbytes;
+      for (int g = 0; g < gc; g += GCH) {
+        uint32_t m[GCH];
+        float2 w[GCH][P];
 #pragma unroll
-          for (int p = 0; p < P; ++p) {
-            const float2 w = a.wk[((g0 + g) * P + p) * 64 + lane];
-            float2 e;
-            if (a.volt_fmt == 0) {
-              const uint16_t v = reinterpret_cast<const uint16_t *>(vs)[ant * P + p];
-              e = make_float2((float)(int8_t)(v & 0xFF), (float)(int8_t)(v >> 8));
-            } else {
-              e = reinterpret_cast<const float2 *>(vs)[ant * P + p];
+        for (int k = 0; k < GCH; ++k) {
+          const bool ok = g + k < gc;
+          m[k] = ok ? a.meta[(g0 + g + k) * 64 + lane] : kEmptyTap;
+#pragma unroll
+          for (int p = 0; p < P; ++p)
+            w[k][p] = ok ? a.wk[((g0 + g + k) * P + p) * 64 + lane] : make_float2(0.f, 0.f);
+        }
+        float2 e[GCH][P];
+#pragma unroll
+        for (int k = 0; k < GCH; ++k) {
+          if (m[k] != kEmptyTap) {
+            load_volt<P>(vrow, a.volt_fmt, (int)(m[k] >> 16), e[k]);
+          } else {
+#pragma unroll
+            for (int p = 0; p < P; ++p) e[k][p] = make_float2(0.f, 0.f);
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < GCH; ++k) {
+          if (m[k] != kEmptyTap) {
+            const int cell = (int)(m[k] & 0xFFFFu);
+            const int rr = cell / N, col = cell - rr * N;
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+              float2 *cellp = grid + (p * HB + rr) * TS + col;
+              const float2 cur = *cellp;
+              const float2 wv = w[k][p], ev = e[k][p];
+              *cellp = make_float2(cur.x + wv.x * ev.x - wv.y * ev.y, cur.y + wv.x * ev.y + wv.y * ev.x);
             }
-            float2 *cellp = grid + (p * hb + rr) * TS + col;
-            const float2 cur = *cellp;
-            *cellp = make_float2(cur.x + w.x * e.x - w.y * e.y, cur.y + w.x * e.y + w.y * e.x);
           }
         }
       }
@@ -261,7 +326,7 @@ __global__ __launch_bounds__(kThreads) void k_rows(RowArgs a) {
       // ROW_FFT: load the band's touched rows from the staged grid
       for (int i = threadIdx.x; i < ntr * N; i += kThreads) {
         const int tr = i / N, col = i - tr * N;
-        const int p = tr / nrow, r = tr - p * nrow;
+        const int p = tr_pol(tr), r = tr - p * nrow;
         grid[tr_base(tr) + col] =
             a.io[(int64_t)t * a.sample_stride + (int64_t)P * a.chans[c].pix_off + (int64_t)p * N * N +
                  (int64_t)(bd.r_lo + r) * N + col];
@@ -270,24 +335,29 @@ __global__ __launch_bounds__(kThreads) void k_rows(RowArgs a) {
     }
 
     if constexpr (MODE == ROW_GRID) {
-      // write the whole band (all its rows) to the staged grid
-      for (int i = threadIdx.x; i < P * bd.rows * N; i += kThreads) {
-        const int pr = i / N, col = i - pr * N;
-        const int p = pr / bd.rows, r = pr - p * bd.rows;
+      // write the band's touched rows to the staged grid (the rest of the grid was cleared beforehand)
+      for (int i = threadIdx.x; i < ntr * N; i += kThreads) {
+        const int tr = i / N, col = i - tr * N;
+        const int p = tr_pol(tr), r = tr - p * nrow;
         a.io[(int64_t)t * a.sample_stride + (int64_t)P * a.chans[c].pix_off + (int64_t)p * N * N +
-             (int64_t)(bd.row0 + r) * N + col] = grid[(p * hb + r) * TS + col];
+             (int64_t)(bd.r_lo + r) * N + col] = grid[tr_base(tr) + col];
       }
       __syncthreads();
     } else {
       // row FFTs of the touched rows
       constexpr int MB0 = (P * HB * (N / PP::R0) + kThreads - 1) / kThreads;
-      auto dst = [&](int tr) -> float2 * {
-        const int p = tr / nrow, r = tr - p * nrow;
-        if constexpr (MODE == ROW_FUSED)
-          return a.io + (((int64_t)(c - a.c0) * a.t_block + (t - a.t0)) * P + p) * N * N + (int64_t)(bd.r_lo + r) * N;
-        else
-          return a.io + (int64_t)t * a.sample_stride + (int64_t)P * a.chans[c].pix_off + (int64_t)p * N * N +
-                 (int64_t)(bd.r_lo + r) * N;
+      // fused: H in column-group tiles [p][q / W][row][q % W], so that each column-pass workgroup reads one
+      // contiguous tile; staged: natural row-major grid
+      auto dst = [&](int tr, int q, float2 v) {
+        const int p = tr_pol(tr), row = bd.r_lo + tr - p * nrow;
+        if constexpr (MODE == ROW_FUSED) {
+          constexpr int W = cols_ce(N);
+          store_stream(a.io + (((int64_t)(c - a.c0) * a.t_block + (t - a.t0)) * P + p) * N * N +
+                           (int64_t)(q / W) * (N * W) + row * W + (q % W), v);
+        } else {
+          a.io[(int64_t)t * a.sample_stride + (int64_t)P * a.chans[c].pix_off + (int64_t)p * N * N +
+               (int64_t)row * N + q] = v;
+        }
       };
       if constexpr (PP::S == 2) {
         constexpr int MB1 = (P * HB * (N / PP::R1) + kThreads - 1) / kThreads;
@@ -310,72 +380,100 @@ __global__ __launch_bounds__(kThreads) void k_rows(RowArgs a) {
 // ------------------------------------------------------------------------------------------------------------
 enum ColMode { COL_FUSED = 0, COL_FFT = 1 };
 
+// Swaps the values of adjacent lanes (quad permutation [1,0,3,2]).
+__device__ __forceinline__ float swap_pair(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+
 template <int N, int P, int W, int MODE, int ACC>
 __global__ __launch_bounds__(kThreads) void k_cols(ColArgs a) {
   using PP = Pipe<N>;
   constexpr int TS = PP::TS;
   constexpr int R0 = PP::R0, NB0 = N / R0;
   constexpr int RL = PP::RLAST, LL = PP::LLAST, NBL = N / RL;
-  constexpr int PR = P == 2 ? 4 : 1;
-  constexpr int MBL = (W * NBL + kThreads - 1) / kThreads;
+  constexpr int NS1 = P * W * NB0;                    // first-stage butterflies per sample
+  constexpr int MB0 = (NS1 + kThreads - 1) / kThreads;
+  constexpr int NSL = P * W * NBL;                    // last-stage butterflies (one pol each)
+  constexpr int MBL = (NSL + kThreads - 1) / kThreads;
+  constexpr int PA = P == 2 ? 2 : 1;                  // accumulator reals per pixel and lane
   extern __shared__ float4 smem4[];
   float2 *buf = reinterpret_cast<float2 *>(smem4);   // [P][W][TS]
-  float2 *tws = buf + P * W * TS;                     // [N]
+  float2 *tws = buf + P * W * TS;                     // [2N] twiddle tables
 
-  // workgroup -> (channel, column group)
-  const int c = a.c0 + (int)(blockIdx.x / (N / W));
-  const int col0 = (int)(blockIdx.x % (N / W)) * W;
+  int c, cg;
+  if constexpr (MODE == COL_FUSED) {
+    if (!cols_xcd_map(a, N / W, c, cg)) return;
+  } else {
+    c = a.c0 + (int)(blockIdx.x / (N / W));
+    cg = (int)(blockIdx.x % (N / W));
+  }
+  const int col0 = cg * W;
   const int jmin = a.chans[c].jmin, jmax = a.chans[c].jmax;
+  const int64_t pstride = (int64_t)N * N;
 
-  for (int i = threadIdx.x; i < N; i += kThreads) tws[i] = a.tw[i];
+  for (int i = threadIdx.x; i < 2 * N; i += kThreads) tws[i] = a.tw[i];
 
-  float acc[MBL][RL][PR];
+  float acc[MBL][RL][PA];
 #pragma unroll
   for (int s = 0; s < MBL; ++s)
 #pragma unroll
     for (int r = 0; r < RL; ++r)
 #pragma unroll
-      for (int k = 0; k < PR; ++k) acc[s][r][k] = 0.f;
+      for (int k = 0; k < PA; ++k) acc[s][r][k] = 0.f;
 
   const int per = (a.nt + (int)gridDim.y - 1) / (int)gridDim.y;
   const int t_begin = a.t0 + (int)blockIdx.y * per;
   const int t_end = min(a.t0 + a.nt, t_begin + per);
-  for (int t = t_begin; t < t_end; ++t) {
-    const float2 *src;
-    int64_t pstride;
-    if constexpr (MODE == COL_FUSED) {
-      src = a.in + ((int64_t)(c - a.c0) * a.t_block + (t - a.t0)) * P * N * N;
-    } else {
-      src = a.in + (int64_t)t * a.sample_stride + (int64_t)P * a.chans[c].pix_off;
-    }
-    pstride = (int64_t)N * N;
-    __syncthreads();   // previous sample's last stage has finished reading buf
-    // first stage: from global (rows outside [jmin, jmax] are zero), straight to the LDS padded layout
-    // (no barrier between read and write: the buffer is not read during this stage)
-    for (int b = threadIdx.x; b < P * W * NB0; b += kThreads) {
+
+  auto sample_src = [&](int t) -> const float2 * {
+    if constexpr (MODE == COL_FUSED)
+      return a.in + ((int64_t)(c - a.c0) * a.t_block + (t - a.t0)) * P * pstride;
+    else
+      return a.in + (int64_t)t * a.sample_stride + (int64_t)P * a.chans[c].pix_off;
+  };
+  // first-stage inputs of one sample, straight from global (rows outside [jmin, jmax] are zero)
+  float2 xs[MB0][R0];
+  auto load_first = [&](int t) {
+    const float2 *src = sample_src(t);
+#pragma unroll
+    for (int s = 0; s < MB0; ++s) {
+      const int b = threadIdx.x + s * kThreads;
       const int col = b % W, p = (b / W) % P, j = b / (W * P);
-      float2 x[R0];
 #pragma unroll
       for (int m = 0; m < R0; ++m) {
         const int row = j + m * NB0;
-        x[m] = (row >= jmin && row <= jmax) ? src[p * pstride + (int64_t)row * N + col0 + col]
-                                            : make_float2(0.f, 0.f);
+        const int64_t off = MODE == COL_FUSED ? (int64_t)col0 * N + row * W + col : (int64_t)row * N + col0 + col;
+        xs[s][m] = (b < NS1 && row >= jmin && row <= jmax) ? load_stream(src + p * pstride + off)
+                                                           : make_float2(0.f, 0.f);
       }
-      dft<R0>(x);
-      float2 *o = buf + (p * W + col) * TS;
-#pragma unroll
-      for (int r = 0; r < R0; ++r) o[pad_addr<N, R0>(j, r)] = x[r];
     }
+  };
+  if (t_begin < t_end) load_first(t_begin);
+
+  for (int t = t_begin; t < t_end; ++t) {
+    __syncthreads();   // the previous sample's last stage has finished reading buf
+#pragma unroll
+    for (int s = 0; s < MB0; ++s) {
+      const int b = threadIdx.x + s * kThreads;
+      if (b < NS1) {
+        const int col = b % W, p = (b / W) % P, j = b / (W * P);
+        dft<R0>(xs[s]);
+        float2 *o = buf + (p * W + col) * TS;
+#pragma unroll
+        for (int r = 0; r < R0; ++r) o[pad_addr<N, R0>(j, r)] = xs[s][r];
+      }
+    }
+    if (t + 1 < t_end) load_first(t + 1);   // in flight during the remaining stages
     __syncthreads();
-    // middle stage (3-stage pipelines)
     if constexpr (PP::S == 3) {
       constexpr int R1 = PP::R1, NB1 = N / R1;
-      constexpr int MB1 = (P * W * NB1 + kThreads - 1) / kThreads;
+      constexpr int NS2 = P * W * NB1;
+      constexpr int MB1 = (NS2 + kThreads - 1) / kThreads;
       float2 x[MB1][R1];
 #pragma unroll
       for (int s = 0; s < MB1; ++s) {
         const int b = threadIdx.x + s * kThreads;
-        if (b < P * W * NB1) {
+        if (b < NS2) {
           const int col = b % W, p = (b / W) % P, j = b / (W * P);
           const float2 *in = buf + (p * W + col) * TS;
 #pragma unroll
@@ -387,7 +485,7 @@ __global__ __launch_bounds__(kThreads) void k_cols(ColArgs a) {
 #pragma unroll
       for (int s = 0; s < MB1; ++s) {
         const int b = threadIdx.x + s * kThreads;
-        if (b < P * W * NB1) {
+        if (b < NS2) {
           const int col = b % W, p = (b / W) % P, j = b / (W * P);
           float2 *o = buf + (p * W + col) * TS;
 #pragma unroll
@@ -396,46 +494,44 @@ __global__ __launch_bounds__(kThreads) void k_cols(ColArgs a) {
       }
       __syncthreads();
     }
-    // last stage: both pols of one (column, butterfly) in one thread
-    {
-      constexpr int RPV = PP::S == 2 ? PP::R0 : PP::R1;
-      constexpr int LPV = PP::S == 2 ? 1 : PP::L1;
+    // last stage: one (pol, column, butterfly) per lane; adjacent lanes hold the two pols of one pixel set
+    constexpr int RPV = PP::S == 2 ? PP::R0 : PP::R1;
+    constexpr int LPV = PP::S == 2 ? 1 : PP::L1;
 #pragma unroll
-      for (int s = 0; s < MBL; ++s) {
-        const int b = threadIdx.x + s * kThreads;
-        if (b < W * NBL) {
-          const int col = b % W, j = b / W;
-          float2 x[P][RL];
+    for (int s = 0; s < MBL; ++s) {
+      const int b0 = threadIdx.x + s * kThreads;
+      const bool valid = b0 < NSL;
+      const int b = valid ? b0 : 0;
+      const int p = P == 2 ? (b & 1) : 0;
+      const int rest = P == 2 ? (b >> 1) : b;
+      const int col = rest % W, j = rest / W;
+      float2 x[RL];
+      const float2 *in = buf + (p * W + col) * TS;
 #pragma unroll
-          for (int p = 0; p < P; ++p) {
-            const float2 *in = buf + (p * W + col) * TS;
+      for (int m = 0; m < RL; ++m) x[m] = in[lds_addr<N, RPV, LPV>(j + m * NBL)];
+      twiddle_dft<N, RL, LL>(x, j, tws);
+      if constexpr (MODE == COL_FUSED) {
 #pragma unroll
-            for (int m = 0; m < RL; ++m) x[p][m] = in[lds_addr<N, RPV, LPV>(j + m * NBL)];
-            twiddle_dft<N, RL, LL>(x[p], j, tws);
-          }
-          if constexpr (MODE == COL_FUSED) {
-#pragma unroll
-            for (int r = 0; r < RL; ++r) {
-              const float2 ex = x[0][r];
-              if constexpr (P == 2) {
-                const float2 ey = x[1][r];
-                acc[s][r][0] += ex.x * ex.x + ex.y * ex.y;
-                acc[s][r][1] += ey.x * ey.x + ey.y * ey.y;
-                acc[s][r][2] += ex.x * ey.x + ex.y * ey.y;   // Re(E_X conj E_Y)
-                acc[s][r][3] += ex.y * ey.x - ex.x * ey.y;   // Im(E_X conj E_Y)
-              } else {
-                acc[s][r][0] += ex.x * ex.x + ex.y * ex.y;
-              }
+        for (int r = 0; r < RL; ++r) {
+          const float2 mine = x[r];
+          if constexpr (P == 2) {
+            const float2 other = make_float2(swap_pair(mine.x), swap_pair(mine.y));
+            const float2 ex = p == 0 ? mine : other, ey = p == 0 ? other : mine;
+            if (valid) {
+              acc[s][r][0] += mine.x * mine.x + mine.y * mine.y;                         // XX or YY
+              acc[s][r][1] += p == 0 ? ex.x * ey.x + ex.y * ey.y : ex.y * ey.x - ex.x * ey.y;  // Re / Im XY
             }
           } else {
-            float2 *dst = a.out + (int64_t)t * a.sample_stride + (int64_t)P * a.chans[c].pix_off;
+            if (valid) acc[s][r][0] += mine.x * mine.x + mine.y * mine.y;
+          }
+        }
+      } else {
+        if (valid) {
+          float2 *dst = a.out + (int64_t)t * a.sample_stride + (int64_t)P * a.chans[c].pix_off;
 #pragma unroll
-            for (int p = 0; p < P; ++p)
-#pragma unroll
-              for (int r = 0; r < RL; ++r) {
-                const int q = nat_out<N, RL, LL>(j, r);
-                dst[p * pstride + (int64_t)q * N + col0 + col] = x[p][r];
-              }
+          for (int r = 0; r < RL; ++r) {
+            const int q = nat_out<N, RL, LL>(j, r);
+            dst[p * pstride + (int64_t)q * N + col0 + col] = x[r];
           }
         }
       }
@@ -443,19 +539,23 @@ __global__ __launch_bounds__(kThreads) void k_cols(ColArgs a) {
   }
 
   if constexpr (MODE == COL_FUSED) {
-    // add the block's FP32 partial sums to the accumulator, one writer per pixel
+    // add the block's FP32 partial sums to the accumulator, one writer per (pixel, real)
+    constexpr int PR = P == 2 ? 4 : 1;
     const int64_t base = (int64_t)PR * a.chans[c].pix_off;
 #pragma unroll
     for (int s = 0; s < MBL; ++s) {
       const int b = threadIdx.x + s * kThreads;
-      if (b < W * NBL) {
-        const int col = b % W, j = b / W;
+      if (b < NSL) {
+        const int p = P == 2 ? (b & 1) : 0;
+        const int rest = P == 2 ? (b >> 1) : b;
+        const int col = rest % W, j = rest / W;
 #pragma unroll
         for (int r = 0; r < RL; ++r) {
           const int q = nat_out<N, RL, LL>(j, r);
 #pragma unroll
-          for (int k = 0; k < PR; ++k) {
-            const int64_t idx = base + (int64_t)k * N * N + (int64_t)q * N + col0 + col;
+          for (int k = 0; k < PA; ++k) {
+            const int prod = P == 2 ? (k == 0 ? p : 2 + p) : 0;   // XX, YY, Re XY, Im XY
+            const int64_t idx = base + (int64_t)prod * pstride + (int64_t)col0 * N + q * W + col;
             if constexpr (ACC == 0) {
               float *o = reinterpret_cast<float *>(a.acc);
               o[idx] += acc[s][r][k];
@@ -510,7 +610,9 @@ __global__ void k_acc_staged(AccArgs a) {
   }
 #pragma unroll
   for (int k = 0; k < PR; ++k) {
-    const int64_t idx = (int64_t)PR * a.chans[c].pix_off + k * nn + local;
+    const int n = a.chans[c].n, W = a.chans[c].cols;
+    const int q = (int)(local / n), pc = (int)(local - (int64_t)q * n);
+    const int64_t idx = (int64_t)PR * a.chans[c].pix_off + k * nn + (int64_t)(pc / W) * n * W + q * W + pc % W;
     if constexpr (ACC == 0) {
       reinterpret_cast<float *>(a.acc)[idx] += s[k];
     } else {
@@ -543,7 +645,8 @@ __global__ void k_read_image(ReadArgs a) {
   const int q = (int)(local / n), pcol = (int)(local - (int64_t)q * n);
   // output pixel (q, p) <- FFT index ((q - n/2) mod n, (p - n/2) mod n)
   const int kq = (q + n / 2) % n, kp = (pcol + n / 2) % n;
-  const int64_t src = (int64_t)kq * n + kp;
+  const int W = a.chans[c].cols;
+  const int64_t src = (int64_t)(kp / W) * n * W + (int64_t)kq * W + kp % W;   // tiled accumulator
   constexpr int PR = P == 2 ? 4 : 1;
   const int64_t abase = (int64_t)PR * a.chans[c].pix_off;
   double v[PR];
@@ -572,17 +675,10 @@ __global__ void k_read_image(ReadArgs a) {
 // Launchers
 // ------------------------------------------------------------------------------------------------------------
 size_t rows_lds_bytes(int n, int P, int band_rows, int A, int volt_fmt) {
-  int ts = 0;
-  switch (n) {
-#define TSCASE(NN) \
-  case NN: ts = Pipe<NN>::TS; break;
-    TSCASE(32) TSCASE(64) TSCASE(96) TSCASE(128) TSCASE(160) TSCASE(192) TSCASE(256) TSCASE(320) TSCASE(384)
-    TSCASE(512)
-#undef TSCASE
-    default: return 0;
-  }
-  const size_t vbytes = (size_t)A * P * (volt_fmt == 0 ? 2 : 8);
-  return (size_t)P * band_rows * ts * 8 + (size_t)n * 8 + ((vbytes + 15) & ~(size_t)15);
+  (void)A;
+  (void)volt_fmt;
+  if (!fft_radix_max(n)) return 0;
+  return (size_t)P * band_rows * row_stride(n) * 8 + (size_t)2 * n * 8;
 }
 
 size_t cols_lds_bytes(int n, int P, int W) {
@@ -595,11 +691,11 @@ size_t cols_lds_bytes(int n, int P, int W) {
 #undef TSCASE
     default: return 0;
   }
-  return (size_t)P * W * ts * 8 + (size_t)n * 8;
+  return (size_t)P * W * ts * 8 + (size_t)2 * n * 8;
 }
 
 // Raises a kernel's dynamic LDS limit to the CU's 160 KB once per kernel and device.
-static hipError_t set_lds_limit(const void *fn) {
+hipError_t set_lds_limit_ext(const void *fn) {
   static std::mutex mu;
   static std::set<std::pair<const void *, int>> done;
   int dev = 0;
@@ -616,7 +712,7 @@ template <int N, int P>
 static hipError_t launch_rows_np(int mode, const RowArgs &a, int grid, size_t lds, hipStream_t st) {
   void (*fn)(RowArgs) = mode == ROW_FUSED ? k_rows<N, P, ROW_FUSED> : mode == ROW_GRID ? k_rows<N, P, ROW_GRID>
                                                                                          : k_rows<N, P, ROW_FFT>;
-  hipError_t e = set_lds_limit((const void *)fn);
+  hipError_t e = set_lds_limit_ext((const void *)fn);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(fn, dim3(grid), dim3(kThreads), lds, st, a);
   return hipGetLastError();
@@ -639,7 +735,7 @@ static hipError_t launch_cols_npw(int mode, int accm, const ColArgs &a, int grid
                                   hipStream_t st) {
   void (*fn)(ColArgs) = mode == COL_FFT ? k_cols<N, P, W, COL_FFT, 0>
                                         : (accm == 0 ? k_cols<N, P, W, COL_FUSED, 0> : k_cols<N, P, W, COL_FUSED, 1>);
-  hipError_t e = set_lds_limit((const void *)fn);
+  hipError_t e = set_lds_limit_ext((const void *)fn);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(fn, dim3(grid, gridy), dim3(kThreads), lds, st, a);
   return hipGetLastError();
@@ -658,12 +754,12 @@ hipError_t launch_cols(int n, int P, int W, int mode, int accm, const ColArgs &a
   // (n, W) pairs follow cols_for(n)
   switch (n) {
     case 32: return W == 32 ? launch_cols_nw<32, 32>(P, mode, accm, a, grid, gridy, lds, st) : hipErrorInvalidValue;
-    case 64: return W == 64 ? launch_cols_nw<64, 64>(P, mode, accm, a, grid, gridy, lds, st) : hipErrorInvalidValue;
-    case 96: return W == 32 ? launch_cols_nw<96, 32>(P, mode, accm, a, grid, gridy, lds, st) : hipErrorInvalidValue;
-    case 128: return W == 32 ? launch_cols_nw<128, 32>(P, mode, accm, a, grid, gridy, lds, st) : hipErrorInvalidValue;
-    case 160: return W == 16 ? launch_cols_nw<160, 16>(P, mode, accm, a, grid, gridy, lds, st) : hipErrorInvalidValue;
-    case 192: return W == 16 ? launch_cols_nw<192, 16>(P, mode, accm, a, grid, gridy, lds, st) : hipErrorInvalidValue;
-    case 256: return W == 16 ? launch_cols_nw<256, 16>(P, mode, accm, a, grid, gridy, lds, st) : hipErrorInvalidValue;
+    case 64: return W == 32 ? launch_cols_nw<64, 32>(P, mode, accm, a, grid, gridy, lds, st) : hipErrorInvalidValue;
+    case 96: return W == 16 ? launch_cols_nw<96, 16>(P, mode, accm, a, grid, gridy, lds, st) : hipErrorInvalidValue;
+    case 128: return W == 16 ? launch_cols_nw<128, 16>(P, mode, accm, a, grid, gridy, lds, st) : hipErrorInvalidValue;
+    case 160: return W == 8 ? launch_cols_nw<160, 8>(P, mode, accm, a, grid, gridy, lds, st) : hipErrorInvalidValue;
+    case 192: return W == 8 ? launch_cols_nw<192, 8>(P, mode, accm, a, grid, gridy, lds, st) : hipErrorInvalidValue;
+    case 256: return W == 8 ? launch_cols_nw<256, 8>(P, mode, accm, a, grid, gridy, lds, st) : hipErrorInvalidValue;
     case 320: return W == 8 ? launch_cols_nw<320, 8>(P, mode, accm, a, grid, gridy, lds, st) : hipErrorInvalidValue;
     case 384: return W == 8 ? launch_cols_nw<384, 8>(P, mode, accm, a, grid, gridy, lds, st) : hipErrorInvalidValue;
     case 512: return W == 8 ? launch_cols_nw<512, 8>(P, mode, accm, a, grid, gridy, lds, st) : hipErrorInvalidValue;
@@ -689,8 +785,25 @@ hipError_t launch_read_image(int P, int accm, const ReadArgs &a, hipStream_t st)
   return hipGetLastError();
 }
 
+int fft_radices(int n, int *r0, int *r1, int *r2) {
+  switch (n) {
+#define FCASE(NN)        \
+  case NN:               \
+    *r0 = Fac<NN>::R0;   \
+    *r1 = Fac<NN>::R1;   \
+    *r2 = Fac<NN>::R2;   \
+    return Fac<NN>::S;
+    FCASE(32) FCASE(64) FCASE(96) FCASE(128) FCASE(160) FCASE(192) FCASE(256) FCASE(320) FCASE(384) FCASE(512)
+#undef FCASE
+    default: return 0;
+  }
+}
+
 hipError_t launch_twiddle(float2 *tw, int n, hipStream_t st) {
-  hipLaunchKernelGGL(k_twiddle_f64, dim3((n + 255) / 256), dim3(256), 0, st, tw, n);
+  int r0, r1, r2;
+  if (!fft_radices(n, &r0, &r1, &r2)) return hipErrorInvalidValue;
+  const int total = r0 * r1 + (r2 > 1 ? n : 0);
+  hipLaunchKernelGGL(k_twiddle_f64, dim3((total + 255) / 256), dim3(256), 0, st, tw, n, r0, r1, r2);
   return hipGetLastError();
 }
 

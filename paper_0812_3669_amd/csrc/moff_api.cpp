@@ -79,7 +79,7 @@ struct ProfScope {
   moff::Plan::ProfRec rec{};
   bool on;
   hipError_t err = hipSuccess;
-  ProfScope(moff::Plan &pl, hipStream_t s, int kind, int64_t cs) : p(pl), st(s), on(pl.profiling) {
+  ProfScope(moff::Plan &pl, hipStream_t s, int kind, int64_t cs) : p(pl), st(s), on(pl.profiling && !pl.capturing) {
     if (!on) return;
     rec.kind = kind;
     rec.cs = cs;
@@ -106,6 +106,70 @@ struct ProfScope {
 int band_begin(const moff::Plan &p, const moff::Block &b) { return p.chans[b.c0].band_first; }
 int band_count(const moff::Plan &p, const moff::Block &b) {
   return p.chans[b.c1 - 1].band_first + p.chans[b.c1 - 1].band_count - p.chans[b.c0].band_first;
+}
+
+moff_status enqueue_correlate(moff::Plan &p, const void *d_volt, int64_t n_t, void *d_acc, hipStream_t st) {
+  float2 *H = reinterpret_cast<float2 *>(ws(p, p.ws_h));
+  moff::RowArgs a = row_args(p, d_volt);
+  a.io = H;
+  moff::ColArgs ca{};
+  ca.chans = d_chans(p);
+  ca.in = H;
+  ca.acc = d_acc;
+  ca.t_block = p.t_block;
+  for (int64_t t0 = 0; t0 < n_t; t0 += p.t_block) {
+    const int nt = (int)std::min<int64_t>(p.t_block, n_t - t0);
+    for (const moff::Block &b : p.blocks) {
+      a.band_begin = band_begin(p, b);
+      a.n_bands = band_count(p, b);
+      a.c0 = b.c0;
+      a.n_chan_block = b.c1 - b.c0;
+      a.t0 = (int)t0;
+      a.nt = nt;
+      a.tw = d_tw(p, b.n);
+      const int tgroups = (nt + p.t_group - 1) / p.t_group;
+      const size_t lds = moff::rows_lds_bytes(b.n, p.n_pol, p.chans[b.c0].band_rows, p.n_ant, p.volt_format);
+      const int64_t cs = (int64_t)nt * (b.c1 - b.c0);
+      const bool split = p.fft_mode != MOFF_FFT_FP32;
+      const int bf16 = p.fft_mode == MOFF_FFT_SPLIT_BF16;
+      const uint16_t *mtab = reinterpret_cast<const uint16_t *>(ws(p, p.ws_mfma));
+      {
+        ProfScope ps(p, st, 0, cs);
+        const int rgrid = moff::rows_xcd_grid(p, b, tgroups);
+        if (split)
+          HIP_TRY(moff::launch_rows_mfma(bf16, a, mtab, rgrid, st), "row pass");
+        else
+          HIP_TRY(moff::launch_rows(b.n, p.n_pol, moff::ROW_MODE_FUSED, a, rgrid, lds, st), "row pass");
+        HIP_TRY(ps.done(), "profile event");
+      }
+      const int W = p.chans[b.c0].cols;
+      ca.c0 = b.c0;
+      ca.t0 = (int)t0;
+      ca.nt = nt;
+      ca.tw = a.tw;
+      const int grid = moff::cols_xcd_grid(b, b.n / W);
+      ca.n_chan_block = b.c1 - b.c0;
+      {
+        ProfScope ps(p, st, 1, cs);
+        if (split)
+          HIP_TRY(moff::launch_cols_mfma(bf16, p.acc_mode, ca, mtab, grid, st), "column pass");
+        else
+          HIP_TRY(moff::launch_cols(b.n, p.n_pol, W, moff::COL_MODE_FUSED, p.acc_mode, ca, grid, 1,
+                                    moff::cols_lds_bytes(b.n, p.n_pol, W), st),
+                  "column pass");
+        HIP_TRY(ps.done(), "profile event");
+      }
+    }
+  }
+  return MOFF_OK;
+}
+
+void drop_graphs(moff::Plan &p) {
+  for (auto &g : p.graphs) {
+    (void)hipGraphExecDestroy(static_cast<hipGraphExec_t>(g.exec));
+    (void)hipGraphDestroy(static_cast<hipGraph_t>(g.graph));
+  }
+  p.graphs.clear();
 }
 
 }  // namespace
@@ -137,12 +201,11 @@ moff_status moff_plan(const moff_plan_desc *desc, moff_plan_t *out) {
     return set_err(s, err);
   }
   const moff::Plan &p = h->p;
-  const size_t vb = (size_t)p.n_ant * p.n_pol * (p.volt_format == MOFF_VOLT_INT8 ? 2 : 8);
   for (const moff::Chan &c : p.chans) {
     if (moff::rows_lds_bytes(c.n, p.n_pol, c.band_rows, p.n_ant, p.volt_format) > (size_t)moff::kMaxLds ||
-        vb > 64 * 1024) {
+        moff::cols_lds_bytes(c.n, p.n_pol, c.cols) > (size_t)moff::kMaxLds) {
       delete h;
-      return set_err(MOFF_E_UNSUPPORTED, "one sample's voltages of a channel exceed the 64 KB LDS staging area");
+      return set_err(MOFF_E_UNSUPPORTED, "grid size needs more LDS than a CU has");
     }
   }
   *out = h;
@@ -151,6 +214,8 @@ moff_status moff_plan(const moff_plan_desc *desc, moff_plan_t *out) {
 
 void moff_plan_destroy(moff_plan_t plan) {
   if (!plan) return;
+  drop_graphs(plan->p);
+  if (plan->p.capture_stream) (void)hipStreamDestroy(static_cast<hipStream_t>(plan->p.capture_stream));
   for (void *e : plan->p.ev_pool) (void)hipEventDestroy(static_cast<hipEvent_t>(e));
   delete plan;
 }
@@ -194,7 +259,9 @@ moff_status moff_bind(moff_plan_t plan, void *d_ws, size_t bytes, void *stream) 
   if (bytes < p.ws_total) return set_err(MOFF_E_BUDGET, "workspace smaller than moff_workspace_size");
   if (reinterpret_cast<uintptr_t>(d_ws) & 255) return set_err(MOFF_E_INVALID, "workspace must be 256-byte aligned");
   hipStream_t st = static_cast<hipStream_t>(stream);
+  drop_graphs(p);
   p.d_ws = d_ws;
+  p.ws_bound = bytes;
   p.bound = false;
   p.kernels_set = false;
   if (!p.bands.empty())
@@ -212,6 +279,10 @@ moff_status moff_bind(moff_plan_t plan, void *d_ws, size_t bytes, void *stream) 
   }
   for (size_t i = 0; i < p.tw_sizes.size(); ++i)
     HIP_TRY(moff::launch_twiddle(reinterpret_cast<float2 *>(ws(p, p.tw_off[i])), p.tw_sizes[i], st), "twiddles");
+  if (p.fft_mode != MOFF_FFT_FP32)
+    HIP_TRY(moff::launch_mfma_table(reinterpret_cast<uint16_t *>(ws(p, p.ws_mfma)),
+                                    p.fft_mode == MOFF_FFT_SPLIT_BF16, st),
+            "split-transform matrices");
   p.bound = true;
   return ok();
 }
@@ -330,47 +401,140 @@ moff_status moff_correlate(moff_plan_t plan, const void *d_volt, int64_t n_t, vo
   if (s) return s;
   if (n_t == 0) return ok();
   if (n_t > INT32_MAX / 2) return set_err(MOFF_E_INVALID, "n_t too large for one call");
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  float2 *H = reinterpret_cast<float2 *>(ws(p, p.ws_h));
-  moff::RowArgs a = row_args(p, d_volt);
-  a.io = H;
-  moff::ColArgs ca{};
-  ca.chans = d_chans(p);
-  ca.in = H;
-  ca.acc = d_acc;
-  ca.t_block = p.t_block;
-  for (int64_t t0 = 0; t0 < n_t; t0 += p.t_block) {
-    const int nt = (int)std::min<int64_t>(p.t_block, n_t - t0);
-    for (const moff::Block &b : p.blocks) {
-      a.band_begin = band_begin(p, b);
-      a.n_bands = band_count(p, b);
-      a.c0 = b.c0;
-      a.t0 = (int)t0;
-      a.nt = nt;
-      a.tw = d_tw(p, b.n);
-      const int tgroups = (nt + p.t_group - 1) / p.t_group;
-      const size_t lds = moff::rows_lds_bytes(b.n, p.n_pol, p.chans[b.c0].band_rows, p.n_ant, p.volt_format);
-      const int64_t cs = (int64_t)nt * (b.c1 - b.c0);
-      {
-        ProfScope ps(p, st, 0, cs);
-        HIP_TRY(moff::launch_rows(b.n, p.n_pol, moff::ROW_MODE_FUSED, a, a.n_bands * tgroups, lds, st), "row pass");
-        HIP_TRY(ps.done(), "profile event");
-      }
-      const int W = p.chans[b.c0].cols;
-      ca.c0 = b.c0;
-      ca.t0 = (int)t0;
-      ca.nt = nt;
-      ca.tw = a.tw;
-      const int grid = (b.c1 - b.c0) * (b.n / W);
-      {
-        ProfScope ps(p, st, 1, cs);
-        HIP_TRY(moff::launch_cols(b.n, p.n_pol, W, moff::COL_MODE_FUSED, p.acc_mode, ca, grid, 1,
-                                  moff::cols_lds_bytes(b.n, p.n_pol, W), st),
-                "column pass");
-        HIP_TRY(ps.done(), "profile event");
-      }
+  s = enqueue_correlate(p, d_volt, n_t, d_acc, static_cast<hipStream_t>(stream));
+  return s ? s : ok();
+}
+
+moff_status moff_correlate_graph(moff_plan_t plan, const void *d_volt, int64_t n_t, void *d_acc, void *stream) {
+  if (!plan) return set_err(MOFF_E_INVALID, "null plan");
+  if (n_t < 0) return set_err(MOFF_E_INVALID, "n_t must be >= 0");
+  if (n_t > 0 && (!d_volt || !d_acc)) return set_err(MOFF_E_INVALID, "null buffer");
+  moff::Plan &p = plan->p;
+  moff_status s = need_bound(p, true);
+  if (s) return s;
+  if (n_t == 0) return ok();
+  if (n_t > INT32_MAX / 2) return set_err(MOFF_E_INVALID, "n_t too large for one call");
+  if (p.profiling) return set_err(MOFF_E_STATE, "graph replay while kernel timing is on");
+  moff::Plan::GraphRec *g = nullptr;
+  for (auto &r : p.graphs)
+    if (r.volt == d_volt && r.nt == n_t && r.acc == d_acc) g = &r;
+  if (!g) {
+    if (!p.capture_stream) {
+      hipStream_t cs;
+      HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "capture stream");
+      p.capture_stream = cs;
     }
+    hipStream_t cs = static_cast<hipStream_t>(p.capture_stream);
+    HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture");
+    p.capturing = true;
+    moff_status es = enqueue_correlate(p, d_volt, n_t, d_acc, cs);
+    p.capturing = false;
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(cs, &graph);
+    if (es) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return es;
+    }
+    if (e != hipSuccess) return hip_fail(e, "end capture");
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      return hip_fail(e, "instantiate graph");
+    }
+    p.graphs.push_back({d_volt, n_t, d_acc, graph, exec});
+    g = &p.graphs.back();
   }
+  HIP_TRY(hipGraphLaunch(static_cast<hipGraphExec_t>(g->exec), static_cast<hipStream_t>(stream)), "graph launch");
+  return ok();
+}
+
+moff_status moff_workspace_size_for(moff_plan_t plan, int32_t time_block, int32_t chans_per_block, size_t *bytes) {
+  if (!plan || !bytes) return set_err(MOFF_E_INVALID, "null argument");
+  if (time_block < 1 || chans_per_block < 1) return set_err(MOFF_E_INVALID, "launch shape must be >= 1");
+  moff::Plan &p = plan->p;
+  const int tb = p.t_block, cpb = p.chans_per_block, tg = p.t_group;
+  *bytes = moff::layout_blocks(p, time_block, chans_per_block, tg);
+  moff::layout_blocks(p, tb, cpb, tg);
+  return ok();
+}
+
+moff_status moff_set_launch_shape(moff_plan_t plan, int32_t time_block, int32_t chans_per_block, int32_t time_group) {
+  if (!plan) return set_err(MOFF_E_INVALID, "null plan");
+  if (time_block < 1 || chans_per_block < 1 || time_group < 1)
+    return set_err(MOFF_E_INVALID, "launch shape must be >= 1");
+  moff::Plan &p = plan->p;
+  const int tb = p.t_block, cpb = p.chans_per_block, tg = p.t_group;
+  const size_t need = moff::layout_blocks(p, time_block, chans_per_block, time_group);
+  if (p.bound && need > p.ws_bound) {
+    moff::layout_blocks(p, tb, cpb, tg);
+    return set_err(MOFF_E_BUDGET, "bound workspace too small for this launch shape");
+  }
+  drop_graphs(p);
+  return ok();
+}
+
+moff_status moff_get_launch_shape(moff_plan_t plan, int32_t *time_block, int32_t *chans_per_block,
+                                  int32_t *time_group) {
+  if (!plan) return set_err(MOFF_E_INVALID, "null plan");
+  if (time_block) *time_block = plan->p.t_block;
+  if (chans_per_block) *chans_per_block = plan->p.chans_per_block;
+  if (time_group) *time_group = plan->p.t_group;
+  return ok();
+}
+
+moff_status moff_autotune(moff_plan_t plan, const void *d_volt, int64_t n_t, void *d_acc, void *stream,
+                          int32_t *time_block, int32_t *chans_per_block, int32_t *time_group, double *best_ms) {
+  if (!plan || !d_volt || !d_acc) return set_err(MOFF_E_INVALID, "null argument");
+  if (n_t < 1 || n_t > INT32_MAX / 2) return set_err(MOFF_E_INVALID, "n_t out of range");
+  moff::Plan &p = plan->p;
+  moff_status s = need_bound(p, true);
+  if (s) return s;
+  if (p.profiling) return set_err(MOFF_E_STATE, "autotune while kernel timing is on");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  static const int tbs[] = {8, 16, 32, 64};
+  static const int cpbs[] = {4, 8, 16, 32, 64, 128};
+  static const int tgs[] = {2, 4, 8, 16, 32, 64};
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0), "event");
+  HIP_TRY(hipEventCreate(&e1), "event");
+  const int tb0 = p.t_block, cpb0 = p.chans_per_block, tg0 = p.t_group;
+  double best = 1e300;
+  int btb = tb0, bcpb = cpb0, btg = tg0;
+  moff_status res = MOFF_OK;
+  for (int tb : tbs) {
+    for (int cpb : cpbs) {
+      for (int tg : tgs) {
+        if (tg > tb) continue;
+        if (moff::layout_blocks(p, tb, cpb, tg) > p.ws_bound) continue;
+        float ms = 0.f;
+        if (enqueue_correlate(p, d_volt, n_t, d_acc, st) != MOFF_OK) { res = MOFF_E_DEVICE; break; }
+        hipError_t e = hipEventRecord(e0, st);
+        if (e == hipSuccess && enqueue_correlate(p, d_volt, n_t, d_acc, st) != MOFF_OK) e = hipErrorUnknown;
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) { res = hip_fail(e, "autotune timing"); break; }
+        if (ms < best) {
+          best = ms;
+          btb = tb;
+          bcpb = cpb;
+          btg = tg;
+        }
+      }
+      if (res) break;
+    }
+    if (res) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  moff::layout_blocks(p, btb, bcpb, btg);
+  drop_graphs(p);
+  if (res) return res;
+  if (time_block) *time_block = btb;
+  if (chans_per_block) *chans_per_block = bcpb;
+  if (time_group) *time_group = btg;
+  if (best_ms) *best_ms = best;
   return ok();
 }
 

@@ -75,11 +75,13 @@ struct Plan {
   size_t ws_bands = 0;                  // Band array (device copy)
   size_t ws_chans = 0;                  // Chan array (device copy)
   size_t ws_meta = 0, ws_kidx = 0, ws_gchan = 0, ws_wk = 0;  // tap groups; packed kernels float2 [G][P][64]
+  size_t ws_mfma = 0;                   // split-transform matrices (split fft modes only)
   size_t ws_h = 0, ws_h_bytes = 0;      // row-pass output of one launch block
   size_t ws_total = 0;
 
   // binding state
   void *d_ws = nullptr;
+  size_t ws_bound = 0;
   bool bound = false, kernels_set = false;
 
   // kernel timing (moff_profile): events are hipEvent_t stored as void*
@@ -89,6 +91,15 @@ struct Plan {
     void *ev0, *ev1;
   };
   bool profiling = false;
+  bool capturing = false;
+  struct GraphRec {
+    const void *volt;
+    int64_t nt;
+    void *acc;
+    void *graph, *exec;   // hipGraph_t, hipGraphExec_t
+  };
+  std::vector<GraphRec> graphs;
+  void *capture_stream = nullptr;   // hipStream_t
   std::vector<ProfRec> prof;
   std::vector<void *> ev_pool;
   size_t ev_used = 0;
@@ -103,6 +114,9 @@ struct Plan {
 
 // Builds the plan; on error returns a status and sets *err.
 moff_status build_plan(const moff_plan_desc &d, Plan &p, std::string *err);
+
+// Launch blocks and the row-transform buffer for a launch shape; returns the workspace bytes it needs.
+size_t layout_blocks(Plan &p, int t_block, int chans_per_block, int t_group);
 
 // True if this build has an FFT pipeline for grid size n.
 bool fft_size_supported(int n);

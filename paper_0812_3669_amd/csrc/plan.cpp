@@ -2,9 +2,11 @@
 // the device workspace layout.  No HIP calls here.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 
+#include "fft_sizes.h"
 #include "moff_plan.h"
 
 namespace moff {
@@ -13,6 +15,15 @@ namespace {
 constexpr double kCLight = 299792458.0;
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+constexpr size_t kMfmaTableBytesHost = (size_t)17 * 2 * 3 * 64 * 8 * 2;   // matrices of the split transform
+
+int env_int(const char *name, int dflt, int lo, int hi) {
+  const char *v = std::getenv(name);
+  if (!v || !*v) return dflt;
+  const long x = std::strtol(v, nullptr, 10);
+  return (int)std::min<long>(hi, std::max<long>(lo, x));
+}
 
 moff_status fail(std::string *err, moff_status s, const std::string &msg) {
   if (err) *err = msg;
@@ -35,9 +46,9 @@ int band_rows_for(int n, int P) {
   return h;
 }
 
-// Columns per workgroup of the column pass: the largest power of two <= max(8, 4096 / n) dividing n.
+// Columns per workgroup of the column pass: the largest power of two <= max(8, 2048 / n) dividing n.
 int cols_for(int n) {
-  int lim = std::max(8, 4096 / n), w = 1;
+  int lim = std::max(8, 2048 / n), w = 1;
   while (w * 2 <= lim && n % (w * 2) == 0) w *= 2;
   return w;
 }
@@ -59,7 +70,6 @@ moff_status build_plan(const moff_plan_desc &d, Plan &p, std::string *err) {
     return fail(err, MOFF_E_INVALID, "cell_lambda must be positive");
   if (d.fft_mode != MOFF_FFT_FP32 && d.fft_mode != MOFF_FFT_SPLIT_FP16 && d.fft_mode != MOFF_FFT_SPLIT_BF16)
     return fail(err, MOFF_E_INVALID, "unknown fft_mode");
-  if (d.fft_mode != MOFF_FFT_FP32) return fail(err, MOFF_E_UNSUPPORTED, "split FFT modes are not built yet");
   if (d.acc_mode != MOFF_ACC_FP32 && d.acc_mode != MOFF_ACC_FP64_COMP)
     return fail(err, MOFF_E_INVALID, "unknown acc_mode");
   if (d.volt_format != MOFF_VOLT_INT8 && d.volt_format != MOFF_VOLT_C64)
@@ -82,8 +92,11 @@ moff_status build_plan(const moff_plan_desc &d, Plan &p, std::string *err) {
     if (!(f > 0.0) || !std::isfinite(f)) return fail(err, MOFF_E_INVALID, "channel frequencies must be positive");
 
   const int A = p.n_ant, C = p.n_chan, K = p.ksize, P = p.n_pol;
-  p.t_block = d.time_block > 0 ? d.time_block : 16;
-  p.t_group = std::min(4, p.t_block);
+  // launch-block shape of the fused path (defaults; MOFF_T_BLOCK, MOFF_T_GROUP, MOFF_CHANS_PER_BLOCK override)
+  if (d.chans_per_block < 0 || d.time_group < 0) return fail(err, MOFF_E_INVALID, "launch shape must be >= 0");
+  const int tb = d.time_block > 0 ? d.time_block : env_int("MOFF_T_BLOCK", 16, 1, 4096);
+  const int tg = d.time_group > 0 ? d.time_group : env_int("MOFF_T_GROUP", 4, 1, 4096);
+  const int cpb = d.chans_per_block > 0 ? d.chans_per_block : env_int("MOFF_CHANS_PER_BLOCK", 16, 1, 1 << 20);
 
   // ---- per-channel grid size and footprints ------------------------------------------------------------
   p.chans.assign(C, Chan{});
@@ -136,6 +149,12 @@ moff_status build_plan(const moff_plan_desc &d, Plan &p, std::string *err) {
     ch.col_groups = n / ch.cols;
   }
   p.pix_total = pix;
+  if (p.fft_mode != MOFF_FFT_FP32) {
+    // the matrix-core transform is built for 256^2 grids with two pols
+    if (P != 2) return fail(err, MOFF_E_UNSUPPORTED, "split-precision transform needs two pols");
+    for (const Chan &ch : p.chans)
+      if (ch.n != 256) return fail(err, MOFF_E_UNSUPPORTED, "split-precision transform is built for 256^2 grids");
+  }
 
   // ---- row bands, band antenna lists and tap groups ------------------------------------------------------
   p.bands.clear();
@@ -164,11 +183,15 @@ moff_status build_plan(const moff_plan_desc &d, Plan &p, std::string *err) {
       }
       const int32_t lo = p.band_ptr.back(), hi = (int32_t)p.band_ant.size();
       p.band_ptr.push_back(hi);
-      // tap groups per wavefront: first fit into groups of 64 distinct cells, antennas ascending, so every cell
-      // receives its contributions in ascending antenna order (deterministic sums, no atomics)
+      // tap groups per wavefront: 64 taps on 64 distinct cells per group, antennas ascending, first fit, so every
+      // cell receives its contributions in ascending antenna order (deterministic sums, no atomics).  Lane
+      // 16 q + k of a group holds a tap whose LDS word offset is k mod 16, so the 16 lanes a quarter-wave
+      // presents to the LDS at once hit 16 different bank pairs.
+      const int ts = row_stride(n);
       for (int w = 0; w < kWaves; ++w) {
         const int64_t g0 = p.n_groups;
         last_used.assign((size_t)bd.rows * n, -1);
+        std::vector<uint64_t> used;      // per group: bit 16 q + k set when lane 16 q + k is taken
         std::vector<int32_t> count;
         int64_t first_open = 0;
         for (int e = lo; e < hi; ++e) {
@@ -179,17 +202,28 @@ moff_status build_plan(const moff_plan_desc &d, Plan &p, std::string *err) {
             if (r < 0 || r >= bd.rows || (r % kWaves) != w) continue;
             for (int x = 0; x < K; ++x) {
               const int cell = r * n + i0 + x;
+              const int key = (r * ts + i0 + x) & 15;
               int64_t g = std::max<int64_t>(first_open, (int64_t)last_used[cell] + 1);
-              while (g < (int64_t)count.size() && count[g] == kGroupLanes) ++g;
-              if (g == (int64_t)count.size()) {
-                count.push_back(0);
-                p.grp_meta.resize(p.grp_meta.size() + kGroupLanes, kEmptyTap);
-                p.grp_kidx.resize(p.grp_kidx.size() + kGroupLanes, -1);
-                p.grp_chan.push_back(c);
+              int lane = -1;
+              for (;; ++g) {
+                if (g == (int64_t)count.size()) {
+                  count.push_back(0);
+                  used.push_back(0);
+                  p.grp_meta.resize(p.grp_meta.size() + kGroupLanes, kEmptyTap);
+                  p.grp_kidx.resize(p.grp_kidx.size() + kGroupLanes, -1);
+                  p.grp_chan.push_back(c);
+                }
+                for (int q = 0; q < 4; ++q)
+                  if (!((used[g] >> (16 * q + key)) & 1)) {
+                    lane = 16 * q + key;
+                    break;
+                  }
+                if (lane >= 0) break;
               }
-              const size_t slot = (size_t)(g0 + g) * kGroupLanes + count[g];
+              const size_t slot = (size_t)(g0 + g) * kGroupLanes + lane;
               p.grp_meta[slot] = ((uint32_t)a << 16) | (uint32_t)cell;
               p.grp_kidx[slot] = (a * K + y) * K + x;
+              used[g] |= (uint64_t)1 << lane;
               ++count[g];
               last_used[cell] = (int32_t)g;
               while (first_open < (int64_t)count.size() && count[first_open] == kGroupLanes) ++first_open;
@@ -206,16 +240,7 @@ moff_status build_plan(const moff_plan_desc &d, Plan &p, std::string *err) {
   }
   if ((int64_t)p.bands.size() > INT32_MAX / 2) return fail(err, MOFF_E_UNSUPPORTED, "too many bands");
 
-  // ---- launch blocks of the fused path: consecutive channels with one grid size -----------------------
-  p.blocks.clear();
-  for (int c = 0; c < C;) {
-    Block b{c, c, p.chans[c].n};
-    while (b.c1 < C && p.chans[b.c1].n == b.n && b.c1 - b.c0 < p.chans_per_block) ++b.c1;
-    p.blocks.push_back(b);
-    c = b.c1;
-  }
-
-  // ---- workspace layout -------------------------------------------------------------------------------------
+  // ---- workspace layout (launch blocks and the row-transform buffer last) -------------------------------
   size_t off = 0;
   p.tw_sizes.clear();
   p.tw_off.clear();
@@ -223,9 +248,9 @@ moff_status build_plan(const moff_plan_desc &d, Plan &p, std::string *err) {
     if (std::find(p.tw_sizes.begin(), p.tw_sizes.end(), p.chans[c].n) == p.tw_sizes.end())
       p.tw_sizes.push_back(p.chans[c].n);
   p.ws_twiddle = off;
-  for (int n : p.tw_sizes) {
+  for (int n : p.tw_sizes) {   // twiddle tables: at most 2n entries per transform length
     p.tw_off.push_back(off);
-    off = align256(off + (size_t)n * 8);
+    off = align256(off + (size_t)2 * n * 8);
   }
   p.ws_bands = off;
   off = align256(off + p.bands.size() * sizeof(Band));
@@ -239,17 +264,33 @@ moff_status build_plan(const moff_plan_desc &d, Plan &p, std::string *err) {
   off = align256(off + p.grp_chan.size() * 4);
   p.ws_wk = off;
   off = align256(off + (size_t)p.n_groups * P * kGroupLanes * 8);
+  p.ws_mfma = off;
+  if (p.fft_mode != MOFF_FFT_FP32) off = align256(off + kMfmaTableBytesHost);
+  p.ws_h = off;
+  layout_blocks(p, tb, cpb, tg);
+  return MOFF_OK;
+}
+
+size_t layout_blocks(Plan &p, int t_block, int chans_per_block, int t_group) {
+  p.t_block = std::max(1, t_block);
+  p.chans_per_block = std::max(1, chans_per_block);
+  p.t_group = std::max(1, std::min(t_group, p.t_block));
+  p.blocks.clear();
+  for (int c = 0; c < p.n_chan;) {
+    Block b{c, c, p.chans[c].n};
+    while (b.c1 < p.n_chan && p.chans[b.c1].n == b.n && b.c1 - b.c0 < p.chans_per_block) ++b.c1;
+    p.blocks.push_back(b);
+    c = b.c1;
+  }
   size_t hmax = 0;
   for (const Block &b : p.blocks) {
     size_t s = 0;
-    for (int c = b.c0; c < b.c1; ++c) s += (size_t)P * p.chans[c].n * p.chans[c].n * 8;
+    for (int c = b.c0; c < b.c1; ++c) s += (size_t)p.n_pol * p.chans[c].n * p.chans[c].n * 8;
     hmax = std::max(hmax, s * (size_t)p.t_block);
   }
-  p.ws_h = off;
   p.ws_h_bytes = hmax;
-  off = align256(off + hmax);
-  p.ws_total = off;
-  return MOFF_OK;
+  p.ws_total = align256(p.ws_h + hmax);
+  return p.ws_total;
 }
 
 }  // namespace moff

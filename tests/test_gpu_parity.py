@@ -227,3 +227,62 @@ def test_hermitian_products_and_positivity():
     assert np.array_equal(im[3], np.conj(im[2]))
     assert im[0].real.min() >= 0 and im[1].real.min() >= 0
     assert np.all(np.abs(im[2]) ** 2 <= im[0].real * im[1].real * (1 + 1e-4) + 1e-3)
+
+
+# ---------------------------------------------------------------------------------------------------------
+# batching: per-channel grid sizes, graph replay, launch shapes, autotuner
+# ---------------------------------------------------------------------------------------------------------
+def test_per_channel_grid_sizes_against_oracle():
+    """Channels spanning 50-200 MHz get grids from 128^2 to 384^2 (6x6 kernels), all in one correlate call."""
+    cfg = configs.scaled(configs.BATCHED, n_ant=48, n_chan=6, n_time=5)
+    geo, kern, volts, plan = _setup(cfg)
+    assert len(set(plan.grid_n)) >= 4, plan.grid_n
+    imgs, _ = _run_fused(plan, volts)
+    ref = ora.image(volts, kern, geo.ant_xy_m, geo.freqs_hz, geo.grid_n, cfg.cell_lambda)
+    _check_images(imgs, ref, label="per-channel sizes")
+
+
+def test_graph_replay_shapes_and_autotune():
+    cfg = _small(128, C=5, A=64, T=40)
+    geo, kern, volts, plan = _setup(cfg)
+    big = max(plan.workspace_bytes_for(tb, cpb) for tb in (8, 16, 32, 64) for cpb in (4, 8, 16, 32, 64, 128))
+    plan.bind(DEV, workspace_bytes=big)
+    plan.set_kernels(torch.from_numpy(kern).to(DEV))
+    v = torch.from_numpy(volts).to(DEV)
+    ref = ora.image(volts, kern, geo.ant_xy_m, geo.freqs_hz, geo.grid_n, cfg.cell_lambda)
+    a_ref = plan.new_accumulator()
+    plan.correlate(v, a_ref)
+    a_g = plan.new_accumulator()
+    for _ in range(3):                       # capture once, replay; eager work in between
+        a_g.zero_()
+        plan.correlate_graph(v, a_g)
+        torch.cuda.synchronize()
+        assert torch.equal(a_g, a_ref)
+    plan.set_launch_shape(8, 2, 2)
+    assert plan.launch_shape() == (8, 2, 2)
+    a2 = plan.new_accumulator()
+    plan.correlate(v, a2)
+    _check_images([im.cpu().numpy().astype(np.complex128) for im in plan.read_image(a2)], ref, label="shape")
+    best = plan.autotune(v, plan.new_accumulator(), n_t=16)
+    assert best["ms"] > 0 and plan.launch_shape() == (best["time_block"], best["chans_per_block"],
+                                                      best["time_group"])
+    a3 = plan.new_accumulator()
+    plan.correlate(v, a3)
+    _check_images([im.cpu().numpy().astype(np.complex128) for im in plan.read_image(a3)], ref, label="tuned")
+
+
+
+# ---------------------------------------------------------------------------------------------------------
+# precision form: both FFT stages on the matrix cores with split FP16 / BF16 products
+# ---------------------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("mode", [api.FFT_SPLIT_FP16, api.FFT_SPLIT_BF16])
+@pytest.mark.parametrize("acc_mode", [api.ACC_FP32, api.ACC_FP64_COMP])
+def test_split_precision_transform(mode, acc_mode):
+    cfg = _small(256, C=2, A=90, T=6, seed=7)
+    geo, kern, volts = synth.workload(cfg)
+    plan = api.plan_for(cfg, geo, fft_mode=mode, acc_mode=acc_mode).bind(DEV)
+    plan.set_kernels(torch.from_numpy(kern).to(DEV))
+    imgs, _ = _run_fused(plan, volts)
+    ref = ora.image(volts, kern, geo.ant_xy_m, geo.freqs_hz, geo.grid_n, cfg.cell_lambda)
+    worst = _check_images(imgs, ref, label=f"split mode {mode}")
+    print(f"split mode {mode} acc {acc_mode}: worst per-image error {worst:.2e}")

@@ -125,3 +125,13 @@ def test_cost_model_counts():
     f = configs.HEADLINE.flops_per_cs()
     assert f == pytest.approx(2 * 5 * 65536 * 16 + 8 * 2048 * 2 * 16 + 16 * 65536)
     assert f / 1e6 == pytest.approx(12.06, abs=0.01)
+
+
+def test_split_precision_transform_needs_256_grids_and_two_pols():
+    xy = np.array([[1.0, 2.0], [-3.0, 4.0]])
+    for kw in (dict(grid_n=[128], n_pol=2), dict(grid_n=[256], n_pol=1)):
+        with pytest.raises(MoffError) as ei:
+            Plan(xy, [configs.C_LIGHT], fft_mode=1, ksize=4, **kw)
+        assert ei.value.status == 4
+    Plan(xy, [configs.C_LIGHT], [256], n_pol=2, ksize=4, fft_mode=1)
+    Plan(xy, [configs.C_LIGHT], [256], n_pol=2, ksize=4, fft_mode=2)

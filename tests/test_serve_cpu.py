@@ -1,0 +1,52 @@
+"""CPU tests of the serving scheduler with a modelled executor: admission by HBM budget and slots, arrival-order
+queueing, rejection of jobs that can never fit, latency accounting."""
+import numpy as np
+
+from paper_0812_3669_amd.serve import JobSpec, ModelExecutor, Scheduler, hbm_bytes, make_trace
+
+
+def test_trace_is_seeded_and_drawn_from_the_sets():
+    a = make_trace(seed=7, n_jobs=64)
+    b = make_trace(seed=7, n_jobs=64)
+    assert [(j.arrival, j.n_ant, j.n_chan, j.n_time, j.grid_n, j.mode) for j in a] == \
+           [(j.arrival, j.n_ant, j.n_chan, j.n_time, j.grid_n, j.mode) for j in b]
+    assert all(j.n_ant in (256, 1024, 4096, 8192) and j.n_chan in (16, 64, 256) for j in a)
+    assert all(j.grid_n in (128, 256, 512) and j.n_time in (1024, 8192, 65536) for j in a)
+    gaps = np.diff([0.0] + [j.arrival for j in make_trace(seed=1, n_jobs=4000)])
+    assert abs(gaps.mean() - 1 / 200.0) < 0.1 / 200.0     # Poisson stream, mean 200 jobs/s
+
+
+def _jobs(n, T=256, chans=16, grid=128, spacing=0.0):
+    return [JobSpec(i, i * spacing, 256, chans, T, grid) for i in range(n)]
+
+
+def test_all_jobs_complete_and_latency_includes_queueing():
+    ex = ModelExecutor(cs_per_s=1e6)
+    sch = Scheduler(ex, hbm_budget=1 << 40, max_slots=2, block=64)
+    st = sch.run(_jobs(6), realtime=False)
+    s = st.summary()
+    assert s["jobs_completed"] == 6 and s["admitted"] == 6 and s["rejected"] == 0
+    assert s["peak_concurrent"] == 2
+    lat = sorted(st.latencies)
+    assert lat[-1] > 2.5 * lat[0]            # the last jobs waited for slots
+    assert st.channel_samples == 6 * 16 * 256
+
+
+def test_budget_limits_concurrency_and_rejects_oversized_jobs():
+    job = JobSpec(0, 0.0, 256, 16, 128, 128)
+    need = hbm_bytes(job, 64)
+    ex = ModelExecutor(cs_per_s=1e6)
+    sch = Scheduler(ex, hbm_budget=int(2.5 * need), max_slots=8, block=64)
+    jobs = _jobs(5, T=128) + [JobSpec(99, 0.0, 8192, 256, 128, 512)]   # the last can never fit
+    st = sch.run(jobs, realtime=False)
+    assert st.rejected == 1 and st.admitted == 5
+    assert st.peak_concurrent == 2
+
+
+def test_arrivals_in_the_future_wait_for_their_time():
+    ex = ModelExecutor(cs_per_s=1e9)
+    sch = Scheduler(ex, hbm_budget=1 << 40, max_slots=4, block=64)
+    st = sch.run(_jobs(3, T=64, spacing=5.0), realtime=False)
+    assert st.summary()["jobs_completed"] == 3
+    assert st.wall >= 10.0
+    assert max(st.latencies) < 0.01
