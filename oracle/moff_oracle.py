@@ -126,13 +126,15 @@ def efield_image(G: np.ndarray, D: Optional[np.ndarray] = None) -> np.ndarray:
 
 
 def efield_pixels(G: np.ndarray, pix: np.ndarray) -> np.ndarray:
-    """E~ at selected pixels only: pix int [M, 2] (q, p); G [T, n, n] -> complex128 [T, M]."""
+    """E~ at selected pixels only: pix int [M, 2] (q, p); G [T, n, n] -> complex128 [T, M].
+
+    The same double sum for each pixel, summed over the column index i first (a matrix product with the
+    selected columns of D), then over the row index j.
+    """
     n = G.shape[-1]
     D = dft_matrix(n)
-    out = np.empty((G.shape[0], pix.shape[0]), dtype=np.complex128)
-    for m, (q, p) in enumerate(pix):
-        out[:, m] = np.einsum("tji,j,i->t", G, D[:, q], D[:, p])
-    return out
+    GD = np.matmul(G, D[:, pix[:, 1]])                     # [T, n (j), M]: sum over i of G[j, i] D[i, p_m]
+    return np.einsum("tjm,jm->tm", GD, D[:, pix[:, 0]])    # sum over j of D[j, q_m] (...)
 
 
 # ---------------------------------------------------------------------------------------------------------
@@ -175,6 +177,40 @@ def image(volts: np.ndarray, kern: np.ndarray, ant_xy_m: np.ndarray, freqs_hz: S
                 acc[k] += pr.sum(axis=0)
         out.append(acc)
     return out
+
+
+def image_jones(volts: np.ndarray, kern: np.ndarray, ant_xy_m: np.ndarray, freqs_hz: Sequence[float],
+                grid_n: Sequence[int], cell_lambda: float, t_batch: int = 16) -> List[np.ndarray]:
+    """The MOFF image with full-polarisation (2 x 2 Jones) kernels: grid p receives every pol q of each antenna,
+    G_p = sum_a sum_q K_{a,pq} E_{a,q} (the polarimetric form of Eq. m6 step 2); the rest as in ``image``.
+
+    kern: complex [C, A, 2 (p), 2 (q), K, K].  Returns a list over channels of complex128 [4, n_c, n_c].
+    """
+    e_all = unpack(volts)
+    T, C, A, P = e_all.shape
+    K = kern.shape[-1]
+    out = []
+    for c in range(C):
+        n = int(grid_n[c])
+        origin = footprint_origin(ant_xy_m, freqs_hz[c], cell_lambda, n, K)
+        D = dft_matrix(n)
+        acc = np.zeros((4, n, n), dtype=np.complex128)
+        for t0 in range(0, T, t_batch):
+            t1 = min(T, t0 + t_batch)
+            ef = []
+            for p in range(2):
+                G = sum(grid_many(e_all[t0:t1, c, :, q], kern[c, :, p, q], origin, n) for q in range(2))
+                ef.append(efield_image(G, D))
+            for k, pr in enumerate(pol_products(ef[0], ef[1])):
+                acc[k] += pr.sum(axis=0)
+        out.append(acc)
+    return out
+
+
+def apply_phases(volts: np.ndarray, phase: np.ndarray) -> np.ndarray:
+    """Phase-centre tracking (Section 4): each antenna's channelised voltage times its phase, before gridding.
+    volts int8 [T, C, A, P, 2] or complex [T, C, A, P]; phase complex [C, A, P] -> complex128 [T, C, A, P]."""
+    return unpack(volts) * phase.astype(np.complex128)[None]
 
 
 def image_pixels(volts: np.ndarray, kern: np.ndarray, ant_xy_m: np.ndarray, freq_hz: float, n: int,

@@ -38,6 +38,32 @@ def fx_image(e: np.ndarray, kern: np.ndarray, origin: np.ndarray, n: int) -> np.
     return np.stack(out)
 
 
+def fx_image_jones(e: np.ndarray, kern: np.ndarray, origin: np.ndarray, n: int) -> np.ndarray:
+    """FX route with 2 x 2 Jones kernels: A_PQ = sum_{a,b,q,r} v_ab^{qr} sum_{taps} K_{a,Pq} conj(K_{b,Qr}),
+    visibilities v_ab^{qr} = sum_t E_{a,q} conj(E_{b,r}); kern [A, 2 (P), 2 (q), K, K]."""
+    T, A, _ = e.shape
+    K = kern.shape[-1]
+    kern = kern.astype(np.complex128)
+    a_idx, b_idx = np.meshgrid(np.arange(A), np.arange(A), indexing="ij")
+    a_idx, b_idx = a_idx.ravel(), b_idx.ravel()
+    out = []
+    for (PP, QQ) in PRODUCT_PAIRS[2]:
+        V = np.zeros((n, n), dtype=np.complex128)
+        for q in range(2):
+            for r in range(2):
+                vis = np.einsum("ta,tb->ab", e[:, :, q], np.conj(e[:, :, r]))[a_idx, b_idx]
+                for ky in range(K):
+                    for kx in range(K):
+                        for ly in range(K):
+                            for lx in range(K):
+                                w = kern[a_idx, PP, q, ky, kx] * np.conj(kern[b_idx, QQ, r, ly, lx]) * vis
+                                dj = (origin[a_idx, 0] + ky - origin[b_idx, 0] - ly) % n
+                                di = (origin[a_idx, 1] + kx - origin[b_idx, 1] - lx) % n
+                                np.add.at(V, (dj, di), w)
+        out.append((n * n) * np.fft.fftshift(np.fft.ifft2(V), axes=(-2, -1)))
+    return np.stack(out)
+
+
 def direct_imaging(e: np.ndarray, cells: np.ndarray, n: int) -> np.ndarray:
     """Delta kernels: antenna a puts E_a on cell (j, i) = cells[a]. e [T, A] -> XX image [n, n]."""
     T = e.shape[0]

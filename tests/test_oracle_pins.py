@@ -11,7 +11,7 @@ import pytest
 
 from oracle import moff_oracle as ora
 from paper_0812_3669_amd import configs, synth
-from tests.fx_pin import direct_imaging, fx_image
+from tests.fx_pin import direct_imaging, fx_image, fx_image_jones
 
 pytestmark = pytest.mark.filterwarnings("ignore::DeprecationWarning")
 
@@ -258,3 +258,45 @@ def test_pixel_route_matches_full_image(dual):
     for k in range(4):
         ref = img[k][pix[:, 0], pix[:, 1]]
         assert np.abs(got[k] - ref).max() < 1e-11 * np.abs(img[k]).max()
+
+
+# ---------------------------------------------------------------------------------------------------------
+# 7. Full-polarisation (Jones) kernels and phase-centre tracking
+# ---------------------------------------------------------------------------------------------------------
+def _jones_kern(kern, rng, leak=0.3):
+    """[C, A, 2, K, K] diagonal kernels -> [C, A, 2, 2, K, K] with random leakage terms."""
+    C, A, P, K, _ = kern.shape
+    J = np.zeros((C, A, 2, 2, K, K), dtype=np.complex64)
+    J[:, :, 0, 0], J[:, :, 1, 1] = kern[:, :, 0], kern[:, :, 1]
+    J[:, :, 0, 1] = leak * (rng.standard_normal((C, A, K, K)) + 1j * rng.standard_normal((C, A, K, K)))
+    J[:, :, 1, 0] = leak * (rng.standard_normal((C, A, K, K)) + 1j * rng.standard_normal((C, A, K, K)))
+    return J
+
+
+def test_jones_fx_identity():
+    cfg, geo, kern, volts = _small(2, A=10, n=24, T=4, seed=4, disk=10.0)
+    J = _jones_kern(kern, np.random.default_rng(0))
+    img = ora.image_jones(volts, J, geo.ant_xy_m, geo.freqs_hz, geo.grid_n, cfg.cell_lambda)[0]
+    origin = _origin(geo.ant_xy_m, geo.freqs_hz[0], cfg.cell_lambda, cfg.grid_n, cfg.ksize)
+    fx = fx_image_jones(ora.unpack(volts)[:, 0], J[0], origin, cfg.grid_n)
+    for k in range(4):
+        assert _peak_err(img[k], fx[k]) < 1e-12
+
+
+def test_jones_with_diagonal_kernels_is_the_diagonal_image(dual):
+    cfg, geo, kern, volts, img = dual
+    J = _jones_kern(kern, np.random.default_rng(0), leak=0.0)
+    img2 = ora.image_jones(volts, J, geo.ant_xy_m, geo.freqs_hz, geo.grid_n, cfg.cell_lambda)[0]
+    assert _peak_err(img2, img) < 1e-13
+
+
+def test_phase_tracking_moves_the_source_to_the_phase_centre():
+    """Phases exp(+2 pi i (u l_s + v m_s)) per antenna (a delay towards the source) move a lone source to the
+    image centre; the image then equals that of a source at the centre."""
+    volts, kern, ant_xy, f, n, cells, s, (qs, ps) = _lone_source_delta(dq=(5, -3))
+    l_s, m_s = (ps - n / 2) / n, (qs - n / 2) / n
+    phase = np.exp(2j * np.pi * (ant_xy[:, 0] * l_s + ant_xy[:, 1] * m_s))[None, :, None]
+    img = ora.image(ora.apply_phases(volts[:, :, :, :], phase), kern, ant_xy, [f], [n], 1.0)[0][0].real
+    assert np.unravel_index(np.argmax(img), img.shape) == (n // 2, n // 2)
+    A = cells.shape[0]
+    assert abs(img[n // 2, n // 2] - A * A * np.sum(np.abs(s) ** 2)) < 1e-9 * A * A * np.sum(np.abs(s) ** 2)
