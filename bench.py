@@ -26,18 +26,23 @@ PEAK_FP32_VECTOR = 157.3e12    # MI355X published FP32 vector peak (packed FP32)
 PEAK_HBM = 8.0e12              # MI355X HBM3E, B/s
 
 
+KERNEL_SOURCES = ("kernels.hip", "kernels_mfma.hip", "kernels.h", "fft_radix.h", "fft_sizes.h", "mfma_fft.h")
+
+
 def _src_hash() -> str:
+    """Hash of the kernel sources (the PMC traffic figures are valid only for the kernels they were taken on)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_0812_3669_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
+    for f in KERNEL_SOURCES:
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def _traffic(kernel: str, launches_cs: float):
-    """HBM bytes per launch of ``kernel`` from the committed rocprofv3 PMC summary, if it was taken on the
-    current kernel sources (else None)."""
+def _traffic(kernel: str, launch_cs: int):
+    """HBM bytes per launch of ``kernel`` from the committed rocprofv3 PMC summary (FETCH_SIZE and WRITE_SIZE,
+    each scaled by what the counter reads for a plain 1 GiB device copy), if it was taken on the current kernel
+    sources and the same channel-samples per launch; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -45,9 +50,10 @@ def _traffic(kernel: str, launches_cs: float):
         d = json.load(open(path))
     except Exception:
         return None
-    if d.get("src_hash") != _src_hash() or kernel not in d.get("kernels", {}):
+    k = d.get("kernels", {}).get(kernel)
+    if d.get("src_hash") != _src_hash() or not k or k.get("channel_samples_per_launch") != launch_cs:
         return None
-    return d["kernels"][kernel].get("bytes_per_launch")
+    return k.get("bytes_per_launch")
 
 
 def cpu_baseline(cfg, geo, kern_np, volts_dev, budget_s: float = 12.0):
@@ -89,7 +95,7 @@ def main():
     ap.add_argument("--time", type=int, default=0, help="samples per step (default: the full 16384)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="tune the launch shape on the first 256 samples")
-    ap.add_argument("--graph", action="store_true", help="replay the correlation from a captured HIP graph")
+    ap.add_argument("--eager", action="store_true", help="launch kernel by kernel instead of replaying a HIP graph")
     ap.add_argument("--calibrate-copy", action="store_true", help="run a 1 GiB device copy (PMC calibration)")
     args = ap.parse_args()
 
@@ -135,7 +141,7 @@ def main():
     torch.cuda.synchronize()
     print("bench: workload resident; warmup", file=sys.stderr, flush=True)
 
-    run = plan.correlate_graph if args.graph else plan.correlate
+    run = plan.correlate if args.eager else plan.correlate_graph
 
     def step():
         acc.zero_()
@@ -145,7 +151,7 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    plan.profile(not args.graph)
+    plan.profile(bool(args.eager))
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record()
@@ -155,7 +161,7 @@ def main():
     torch.cuda.synchronize()
     plan.profile(False)
     ms = e0.elapsed_time(e1) / args.steps
-    if args.graph:
+    if not args.eager:
         # kernel timing needs the eager path (events cannot be recorded inside the replayed graph): one extra,
         # untimed step with per-launch events
         plan.profile(True)
@@ -182,7 +188,8 @@ def main():
     per_launch_flops = flops[dom] * d["cs"] / max(d["launches"], 1)
     achieved = per_launch_flops / (avg_ms / 1e3)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP32_VECTOR, "traffic": _traffic(names[dom], None),
+                "frac": achieved / PEAK_FP32_VECTOR,
+                "traffic": _traffic(names[dom], round(d["cs"] / max(d["launches"], 1))),
                 "kernel": names[dom], "avg_launch_ms": avg_ms,
                 "kernel_share": {names[k]: kt[k]["ms"] / (kt[0]["ms"] + kt[1]["ms"]) for k in kt}}
 
@@ -198,7 +205,7 @@ def main():
                    "channel_samples_per_step": cs, "accumulator": args.acc,
                    "fft": args.fft,
                    "launch_shape": dict(zip(("time_block", "chans_per_block", "time_group"), plan.launch_shape())),
-                   "graph_replay": bool(args.graph),
+                   "graph_replay": not args.eager,
                    "algorithmic_flops_per_cs": cfg.flops_per_cs(),
                    "achieved_algorithmic_tflops": value * cfg.flops_per_cs() / 1e12},
         "roofline": roofline,

@@ -30,7 +30,8 @@
  * Layouts (all little-endian, densely packed):
  *   voltages    int8  [n_t][C][A][P][2] (re, im)            (volt_format MOFF_VOLT_INT8)
  *               float [n_t][C][A][P][2] (complex64)          (volt_format MOFF_VOLT_C64)
- *   kernels     float [C][A][P][K][K][2] (complex64), the weight N~ already folded in
+ *   kernels     float [C][A][P][K][K][2] (complex64), the weight N~ already folded in (diagonal kernels);
+ *               float [C][A][2 (p, grid)][2 (q, voltage)][K][K][2] for Jones kernels
  *   grid/efield float [n_t][sum_c P n_c^2][2]: per sample, channel c's block starts at P * pix_off(c), pol p at
  *               + p n_c^2, row-major [j][i].  E-field images are in FFT order: index k <-> pixel (k + n/2) mod n.
  *   accumulator float (MOFF_ACC_FP32) or double pairs (sum, carry) (MOFF_ACC_FP64_COMP), R reals per pixel:
@@ -65,6 +66,9 @@ typedef enum {
 typedef enum { MOFF_FFT_FP32 = 0, MOFF_FFT_SPLIT_FP16 = 1, MOFF_FFT_SPLIT_BF16 = 2 } moff_fft_mode;
 typedef enum { MOFF_ACC_FP32 = 0, MOFF_ACC_FP64_COMP = 1 } moff_acc_mode;
 typedef enum { MOFF_VOLT_INT8 = 0, MOFF_VOLT_C64 = 1 } moff_volt_format;
+/* Diagonal kernels: the X grid receives only X voltages (through K_{a,X}) and the Y grid only Y voltages.
+ * Jones kernels (full polarimetry): grid p receives both pols of every antenna, G_p = sum_q K_{a,pq} E_{a,q}. */
+typedef enum { MOFF_KERNEL_DIAG = 0, MOFF_KERNEL_JONES = 1 } moff_kernel_mode;
 
 typedef struct {
   int32_t n_ant;            /* A >= 1 */
@@ -77,10 +81,11 @@ typedef struct {
   double cell_lambda;       /* grid cell size in wavelengths (> 0) */
   int32_t fft_mode;         /* moff_fft_mode */
   int32_t acc_mode;         /* moff_acc_mode */
-  int32_t time_block;       /* samples per fused launch block (0 = library default, 16) */
+  int32_t time_block;       /* samples per fused launch block (0 = library default, 64) */
   int32_t volt_format;      /* moff_volt_format */
-  int32_t chans_per_block;  /* channels per fused launch block (0 = library default, 16) */
+  int32_t chans_per_block;  /* channels per fused launch block (0 = library default, 64) */
   int32_t time_group;       /* samples per row-pass workgroup (0 = library default, 4) */
+  int32_t kernel_mode;      /* moff_kernel_mode; Jones needs n_pol = 2 and the FP32 transform */
 } moff_plan_desc;
 
 /* Host only.  Validates the description, computes every antenna's footprint per channel, bins antennas into
@@ -108,6 +113,13 @@ moff_status moff_bind(moff_plan_t plan, void *d_ws, size_t bytes, void *stream);
  * order inside the workspace; d_kern may be freed once the stream has passed this call.  Step 1-2 of Eq. m6:
  * the caller folds N~ into the kernels. */
 moff_status moff_set_kernels(moff_plan_t plan, const void *d_kern, void *stream);
+
+/* Phase-centre tracking (Section 4: the phase centre is followed by delaying each antenna's signal before
+ * gridding): as moff_set_kernels, with every antenna's channelised voltage multiplied by d_phase[c][a][p]
+ * (complex64, device) before gridding.  The product is folded into the packed kernels (W (phi E) = (W phi) E),
+ * so the hot path does no extra work; call it again with new phases between time blocks to track a moving phase
+ * centre.  d_phase == NULL is moff_set_kernels. */
+moff_status moff_set_kernels_phased(moff_plan_t plan, const void *d_kern, const void *d_phase, void *stream);
 
 /* Staged path, step 2 (gridding): d_volt [n_t] samples -> d_grid [n_t] grids (layout above, fully written). */
 moff_status moff_grid(moff_plan_t plan, const void *d_volt, int64_t n_t, void *d_grid, void *stream);

@@ -13,6 +13,7 @@ MOFF_OK, MOFF_E_INVALID, MOFF_E_BUDGET, MOFF_E_DEVICE, MOFF_E_UNSUPPORTED, MOFF_
 FFT_FP32, FFT_SPLIT_FP16, FFT_SPLIT_BF16 = range(3)
 ACC_FP32, ACC_FP64_COMP = range(2)
 VOLT_INT8, VOLT_C64 = range(2)
+KERNEL_DIAG, KERNEL_JONES = range(2)
 
 
 class PlanDesc(C.Structure):
@@ -21,7 +22,7 @@ class PlanDesc(C.Structure):
         ("ant_xy_m", C.POINTER(C.c_double)), ("freq_hz", C.POINTER(C.c_double)),
         ("grid_n", C.POINTER(C.c_int32)), ("cell_lambda", C.c_double),
         ("fft_mode", C.c_int32), ("acc_mode", C.c_int32), ("time_block", C.c_int32), ("volt_format", C.c_int32),
-        ("chans_per_block", C.c_int32), ("time_group", C.c_int32),
+        ("chans_per_block", C.c_int32), ("time_group", C.c_int32), ("kernel_mode", C.c_int32),
     ]
 
 
@@ -35,6 +36,7 @@ _SIGS = {
     "moff_chan_offset": ([_P, C.c_int32, C.POINTER(C.c_int64)], C.c_int),
     "moff_bind": ([_P, _P, C.c_size_t, _P], C.c_int),
     "moff_set_kernels": ([_P, _P, _P], C.c_int),
+    "moff_set_kernels_phased": ([_P, _P, _P, _P], C.c_int),
     "moff_grid": ([_P, _P, C.c_int64, _P, _P], C.c_int),
     "moff_fft": ([_P, _P, C.c_int64, _P], C.c_int),
     "moff_accumulate": ([_P, _P, C.c_int64, _P, _P], C.c_int),

@@ -16,7 +16,7 @@ import numpy as np
 
 from . import _lib
 from ._lib import (ACC_FP32, ACC_FP64_COMP, FFT_FP32, FFT_SPLIT_BF16, FFT_SPLIT_FP16,  # noqa: F401
-                   VOLT_C64, VOLT_INT8)
+                   KERNEL_DIAG, KERNEL_JONES, VOLT_C64, VOLT_INT8)
 
 
 class MoffError(RuntimeError):
@@ -48,12 +48,13 @@ class Plan:
 
     def __init__(self, ant_xy_m, freqs_hz, grid_n=None, n_pol: int = 2, ksize: int = 4, cell_lambda: float = 1.0,
                  fft_mode: int = FFT_FP32, acc_mode: int = ACC_FP32, time_block: int = 0,
-                 volt_format: int = VOLT_INT8, chans_per_block: int = 0, time_group: int = 0):
+                 volt_format: int = VOLT_INT8, chans_per_block: int = 0, time_group: int = 0,
+                 kernel_mode: int = KERNEL_DIAG):
         self.lib = _lib.load()
         xy = np.ascontiguousarray(ant_xy_m, dtype=np.float64)
         fr = np.ascontiguousarray(freqs_hz, dtype=np.float64)
         self.n_ant, self.n_chan, self.n_pol, self.ksize = xy.shape[0], fr.shape[0], n_pol, ksize
-        self.acc_mode, self.volt_format = acc_mode, volt_format
+        self.acc_mode, self.volt_format, self.kernel_mode = acc_mode, volt_format, kernel_mode
         gn = None
         if grid_n is not None:
             gn = np.ascontiguousarray(np.broadcast_to(np.asarray(grid_n, dtype=np.int32), (self.n_chan,)))
@@ -64,7 +65,7 @@ class Plan:
         d.grid_n = gn.ctypes.data_as(C.POINTER(C.c_int32)) if gn is not None else None
         d.cell_lambda = cell_lambda
         d.fft_mode, d.acc_mode, d.time_block, d.volt_format = fft_mode, acc_mode, time_block, volt_format
-        d.chans_per_block, d.time_group = chans_per_block, time_group
+        d.chans_per_block, d.time_group, d.kernel_mode = chans_per_block, time_group, kernel_mode
         h = C.c_void_p()
         _check(self.lib.moff_plan(C.byref(d), C.byref(h)), "moff_plan")
         self._h = h
@@ -125,13 +126,26 @@ class Plan:
         self.device = self._ws.device
         return self
 
-    def set_kernels(self, kern, stream=None):
-        """kern: complex64 [C, A, P, K, K] on the device (the noise weight folded in)."""
+    def _kernel_shape(self):
+        if self.kernel_mode == KERNEL_JONES:
+            return (self.n_chan, self.n_ant, 2, 2, self.ksize, self.ksize)
+        return (self.n_chan, self.n_ant, self.n_pol, self.ksize, self.ksize)
+
+    def set_kernels(self, kern, stream=None, phase=None):
+        """kern: complex64 on the device, [C, A, P, K, K] (diagonal) or [C, A, 2, 2, K, K] (Jones; [.., p, q, ..]
+        maps voltage pol q into grid p), the noise weight folded in.  phase: optional complex64 [C, A, P] that
+        multiplies each voltage before gridding (phase-centre tracking)."""
         import torch
         assert kern.dtype == torch.complex64 and kern.is_contiguous()
-        assert tuple(kern.shape) == (self.n_chan, self.n_ant, self.n_pol, self.ksize, self.ksize), kern.shape
-        _check(self.lib.moff_set_kernels(self._h, _ptr(kern), _stream_handle(stream)), "moff_set_kernels")
-        self._kern_ref = kern   # keep alive until the packing kernel has run
+        assert tuple(kern.shape) == self._kernel_shape(), kern.shape
+        if phase is None:
+            _check(self.lib.moff_set_kernels(self._h, _ptr(kern), _stream_handle(stream)), "moff_set_kernels")
+        else:
+            assert phase.dtype == torch.complex64 and phase.is_contiguous()
+            assert tuple(phase.shape) == (self.n_chan, self.n_ant, self.n_pol), phase.shape
+            _check(self.lib.moff_set_kernels_phased(self._h, _ptr(kern), _ptr(phase), _stream_handle(stream)),
+                   "moff_set_kernels_phased")
+        self._kern_ref = (kern, phase)   # keep alive until the packing kernel has run
         return self
 
     def new_accumulator(self):

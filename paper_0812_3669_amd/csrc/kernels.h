@@ -138,14 +138,14 @@ enum { COL_MODE_FUSED = 0, COL_MODE_FFT = 1 };
 
 size_t rows_lds_bytes(int n, int P, int band_rows, int A, int volt_fmt);
 size_t cols_lds_bytes(int n, int P, int W);
-hipError_t launch_rows(int n, int P, int mode, const RowArgs &a, int grid, size_t lds, hipStream_t st);
+hipError_t launch_rows(int n, int P, int mode, bool jones, const RowArgs &a, int grid, size_t lds, hipStream_t st);
 hipError_t launch_cols(int n, int P, int W, int mode, int accm, const ColArgs &a, int grid, int gridy, size_t lds,
                        hipStream_t st);
 hipError_t launch_acc_staged(int P, int accm, const AccArgs &a, hipStream_t st);
 hipError_t launch_read_image(int P, int accm, const ReadArgs &a, hipStream_t st);
 hipError_t launch_twiddle(float2 *tw, int n, hipStream_t st);
-hipError_t launch_pack_kernels(const float2 *kern, const int32_t *kidx, const int32_t *grp_chan, float2 *wk,
-                               int64_t n_groups, int A, int P, int KK, hipStream_t st);
+hipError_t launch_pack_kernels(const float2 *kern, const float2 *phase, const int32_t *kidx, const int32_t *grp_chan,
+                               float2 *wk, int64_t n_groups, int A, int P, int KK, int planes, hipStream_t st);
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t st);
 hipError_t launch_unpack_debug(const void *volt, int fmt, float2 *out, int64_t count, hipStream_t st);
 hipError_t set_lds_limit_ext(const void *fn);

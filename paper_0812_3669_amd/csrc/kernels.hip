@@ -58,23 +58,27 @@ __global__ void k_twiddle_f64(float2 *tw, int n, int r0, int r1, int r2) {
   tw[e] = make_float2((float)c, (float)s);
 }
 
-// Packs the caller's kernels [C][A][P][K*K] into tap-group order wk[g][p][lane].
-__global__ void k_pack_kernels(const float2 *__restrict__ kern, const int32_t *__restrict__ kidx,
-                               const int32_t *__restrict__ grp_chan, float2 *__restrict__ wk, int64_t n_groups,
-                               int A, int P, int KK) {
+// Packs the caller's kernels into tap-group order wk[g][plane][lane]: diagonal kernels [C][A][P][K*K] give P
+// planes, Jones kernels [C][A][2][2][K*K] give planes 2 p + q.  Each is multiplied by the phase-centre phase of
+// the voltage it multiplies, phase[c][a][q], when one is given (W (phi E) = (W phi) E).
+__global__ void k_pack_kernels(const float2 *__restrict__ kern, const float2 *__restrict__ phase,
+                               const int32_t *__restrict__ kidx, const int32_t *__restrict__ grp_chan,
+                               float2 *__restrict__ wk, int64_t n_groups, int A, int P, int KK, int planes) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // over groups x 64 lanes
   if (i >= n_groups * 64) return;
   const int64_t g = i >> 6;
   const int lane = (int)(i & 63);
   const int32_t k = kidx[i];
   const int c = grp_chan[g];
-  for (int p = 0; p < P; ++p) {
+  for (int pl = 0; pl < planes; ++pl) {
     float2 v = make_float2(0.f, 0.f);
     if (k >= 0) {
       const int a = k / KK, tap = k - a * KK;
-      v = kern[(((int64_t)c * A + a) * P + p) * KK + tap];
+      const int q = planes == 4 ? (pl & 1) : pl;   // pol of the voltage this plane multiplies
+      v = kern[(((int64_t)c * A + a) * planes + pl) * KK + tap];
+      if (phase) v = cmul(v, phase[((int64_t)c * A + a) * P + q]);
     }
-    wk[(g * P + p) * 64 + lane] = v;
+    wk[(g * planes + pl) * 64 + lane] = v;
   }
 }
 
@@ -231,8 +235,10 @@ __device__ __forceinline__ void load_volt(const void *row, int fmt, int ant, flo
   }
 }
 
-template <int N, int P, int MODE>
+template <int N, int P, int MODE, bool KJ>
 __global__ __launch_bounds__(kThreads) void k_rows(RowArgs a) {
+  static_assert(!KJ || P == 2, "Jones kernels need two pols");
+  constexpr int PL = KJ ? 4 : P;                      // packed kernel planes
   using PP = Pipe<N>;
   constexpr int TS = row_stride(N);   // even: rows start on 16-byte boundaries
   static_assert(TS >= N + PP::RMAX - 1, "row stride too small for the padded layout");
@@ -287,14 +293,14 @@ __global__ __launch_bounds__(kThreads) void k_rows(RowArgs a) {
       const char *vrow = reinterpret_cast<const char *>(a.volt) + ((int64_t)t * a.n_chan + c) * vbytes;
       for (int g = 0; g < gc; g += GCH) {
         uint32_t m[GCH];
-        float2 w[GCH][P];
+        float2 w[GCH][PL];
 #pragma unroll
         for (int k = 0; k < GCH; ++k) {
           const bool ok = g + k < gc;
           m[k] = ok ? a.meta[(g0 + g + k) * 64 + lane] : kEmptyTap;
 #pragma unroll
-          for (int p = 0; p < P; ++p)
-            w[k][p] = ok ? a.wk[((g0 + g + k) * P + p) * 64 + lane] : make_float2(0.f, 0.f);
+          for (int p = 0; p < PL; ++p)
+            w[k][p] = ok ? a.wk[((g0 + g + k) * PL + p) * 64 + lane] : make_float2(0.f, 0.f);
         }
         float2 e[GCH][P];
 #pragma unroll
@@ -314,9 +320,19 @@ __global__ __launch_bounds__(kThreads) void k_rows(RowArgs a) {
 #pragma unroll
             for (int p = 0; p < P; ++p) {
               float2 *cellp = grid + (p * HB + rr) * TS + col;
-              const float2 cur = *cellp;
-              const float2 wv = w[k][p], ev = e[k][p];
-              *cellp = make_float2(cur.x + wv.x * ev.x - wv.y * ev.y, cur.y + wv.x * ev.y + wv.y * ev.x);
+              float2 cur = *cellp;
+              if constexpr (KJ) {
+                // grid p receives both pols: K_{p0} E_0 + K_{p1} E_1
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                  const float2 wv = w[k][2 * p + q], ev = e[k][q];
+                  cur = make_float2(cur.x + wv.x * ev.x - wv.y * ev.y, cur.y + wv.x * ev.y + wv.y * ev.x);
+                }
+              } else {
+                const float2 wv = w[k][p], ev = e[k][p];
+                cur = make_float2(cur.x + wv.x * ev.x - wv.y * ev.y, cur.y + wv.x * ev.y + wv.y * ev.x);
+              }
+              *cellp = cur;
             }
           }
         }
@@ -709,20 +725,27 @@ hipError_t set_lds_limit_ext(const void *fn) {
 }
 
 template <int N, int P>
-static hipError_t launch_rows_np(int mode, const RowArgs &a, int grid, size_t lds, hipStream_t st) {
-  void (*fn)(RowArgs) = mode == ROW_FUSED ? k_rows<N, P, ROW_FUSED> : mode == ROW_GRID ? k_rows<N, P, ROW_GRID>
-                                                                                         : k_rows<N, P, ROW_FFT>;
+static hipError_t launch_rows_np(int mode, bool jones, const RowArgs &a, int grid, size_t lds, hipStream_t st) {
+  void (*fn)(RowArgs) = nullptr;
+  if constexpr (P == 2) {
+    if (jones) fn = mode == ROW_FUSED ? k_rows<N, P, ROW_FUSED, true> : k_rows<N, P, ROW_GRID, true>;
+  }
+  if (!fn)
+    fn = mode == ROW_FUSED ? k_rows<N, P, ROW_FUSED, false>
+                           : mode == ROW_GRID ? k_rows<N, P, ROW_GRID, false> : k_rows<N, P, ROW_FFT, false>;
   hipError_t e = set_lds_limit_ext((const void *)fn);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(fn, dim3(grid), dim3(kThreads), lds, st, a);
   return hipGetLastError();
 }
 
-hipError_t launch_rows(int n, int P, int mode, const RowArgs &a, int grid, size_t lds, hipStream_t st) {
+hipError_t launch_rows(int n, int P, int mode, bool jones, const RowArgs &a, int grid, size_t lds, hipStream_t st) {
   if (grid <= 0) return hipSuccess;
+  if (jones && (P != 2 || mode == ROW_FFT)) return hipErrorInvalidValue;
 #define RCASE(NN)                                                                                \
   case NN:                                                                                       \
-    return P == 2 ? launch_rows_np<NN, 2>(mode, a, grid, lds, st) : launch_rows_np<NN, 1>(mode, a, grid, lds, st);
+    return P == 2 ? launch_rows_np<NN, 2>(mode, jones, a, grid, lds, st)                         \
+                  : launch_rows_np<NN, 1>(mode, jones, a, grid, lds, st);
   switch (n) {
     RCASE(32) RCASE(64) RCASE(96) RCASE(128) RCASE(160) RCASE(192) RCASE(256) RCASE(320) RCASE(384) RCASE(512)
     default: return hipErrorInvalidValue;
@@ -807,12 +830,12 @@ hipError_t launch_twiddle(float2 *tw, int n, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_pack_kernels(const float2 *kern, const int32_t *kidx, const int32_t *grp_chan, float2 *wk,
-                               int64_t n_groups, int A, int P, int KK, hipStream_t st) {
+hipError_t launch_pack_kernels(const float2 *kern, const float2 *phase, const int32_t *kidx, const int32_t *grp_chan,
+                               float2 *wk, int64_t n_groups, int A, int P, int KK, int planes, hipStream_t st) {
   const int64_t total = n_groups * 64;
   if (total == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_pack_kernels, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, kern, kidx,
-                     grp_chan, wk, n_groups, A, P, KK);
+  hipLaunchKernelGGL(k_pack_kernels, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, kern, phase, kidx,
+                     grp_chan, wk, n_groups, A, P, KK, planes);
   return hipGetLastError();
 }
 

@@ -74,6 +74,8 @@ __global__ __launch_bounds__(kThreads) void k_rows_mfma(RowArgs a, const uint16_
   const int gc = bp->grp_cnt[wave];
   const size_t vbytes = (size_t)a.n_ant * MP * (a.volt_fmt == 0 ? 2 : 8);
   constexpr int GCH = 8;
+  MfmaMats<BF16> mats;
+  mats.load(table, lane, wave);
 
   for (int t = t_lo; t < t_hi; ++t) {
     {
@@ -129,7 +131,7 @@ __global__ __launch_bounds__(kThreads) void k_rows_mfma(RowArgs a, const uint16_
     __syncthreads();
     // 16 row transforms (pol p, band row r) = transform p * 8 + r; outputs back into the grid (its reads
     // finished at the barrier inside the FFT)
-    fft256x16_mfma<BF16>(grid, MTS, ys, table,
+    fft256x16_mfma<BF16>(grid, MTS, ys, mats,
                          [&](int tt, int q, float2 v, int, int) { grid[tt * MTS + q] = v; });
     __syncthreads();
     // touched rows to the column-group tiles of H: [p][q / W][row][q % W], 8 rows x 8 columns contiguous
@@ -160,6 +162,8 @@ __global__ __launch_bounds__(kThreads) void k_cols_mfma(ColArgs a, const uint16_
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int tt = lane & 15, g = lane >> 4;
   const int p = tt >> 3, col = tt & 7;
+  MfmaMats<BF16> mats;
+  mats.load(table, lane, wave);
 
   float acc[4][4][2];
 #pragma unroll
@@ -177,7 +181,7 @@ __global__ __launch_bounds__(kThreads) void k_cols_mfma(ColArgs a, const uint16_
           (row >= jmin && row <= jmax) ? load_stream(src + (int64_t)pp * MN * MN + rem) : make_float2(0.f, 0.f);
     }
     __syncthreads();
-    fft256x16_mfma<BF16>(xs, MTS, ys, table, [&](int, int, float2 v, int jj, int i) {
+    fft256x16_mfma<BF16>(xs, MTS, ys, mats, [&](int, int, float2 v, int jj, int i) {
       // lanes t and t ^ 8 hold the two pols of one pixel
       const float2 o = make_float2(__shfl_xor(v.x, 8), __shfl_xor(v.y, 8));
       const float2 ex = p == 0 ? v : o, ey = p == 0 ? o : v;

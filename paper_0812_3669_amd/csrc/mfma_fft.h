@@ -103,12 +103,40 @@ struct MfmaOps<true> {
   }
 };
 
-// One radix-16 DFT-GEMM over 16 transforms: lane (g = l / 16, t = l % 16) supplies x[8 (g & 1) + i] of component
-// (g >> 1) (0 Re, 1 Im) of transform t and receives y[4 g + i] (Re, Im) of transform t.  amat: the matrix's table
-// entry (Re part at +0, Im part at + kMfmaTerms * 64 * 8 halfs).
+// The matrix operands a wavefront needs, loaded once and kept in registers: stage 1, and the stage-2 matrices
+// of the four butterflies j2 = 4 w + jj the wavefront computes.
 template <bool BF16>
-__device__ __forceinline__ void dft16_mfma(const float (&xin)[8], const uint16_t *__restrict__ amat, int lane,
-                                           float (&yre)[4], float (&yim)[4]) {
+struct MfmaMats {
+  using V = typename MfmaOps<BF16>::vec;
+  V s1[2][3];        // [part][term]
+  V s2[4][2][3];     // [jj][part][term]
+  __device__ void load(const uint16_t *__restrict__ table, int lane, int wave) {
+    constexpr size_t kMat = (size_t)2 * kMfmaTerms * 64 * 8;
+#pragma unroll
+    for (int part = 0; part < 2; ++part)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        if (k < MfmaOps<BF16>::terms) {
+          s1[part][k] = MfmaOps<BF16>::load(table + ((size_t)(part * kMfmaTerms + k) * 64 + lane) * 8);
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj)
+            s2[jj][part][k] = MfmaOps<BF16>::load(table + (size_t)(1 + 4 * wave + jj) * kMat +
+                                                  ((size_t)(part * kMfmaTerms + k) * 64 + lane) * 8);
+        } else {
+          s1[part][k] = V{};
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj) s2[jj][part][k] = V{};
+        }
+      }
+  }
+};
+
+// One radix-16 DFT-GEMM over 16 transforms: lane (g = l / 16, t = l % 16) supplies x[8 (g & 1) + i] of component
+// (g >> 1) (0 Re, 1 Im) of transform t and receives y[4 g + i] (Re, Im) of transform t.
+template <bool BF16>
+__device__ __forceinline__ void dft16_mfma(const float (&xin)[8], const typename MfmaOps<BF16>::vec (&are)[3],
+                                           const typename MfmaOps<BF16>::vec (&aim)[3], float (&yre)[4],
+                                           float (&yim)[4]) {
   using O = MfmaOps<BF16>;
   float x[8];
   float s = 1.f, inv = 1.f;
@@ -130,16 +158,6 @@ __device__ __forceinline__ void dft16_mfma(const float (&xin)[8], const uint16_t
   for (int i = 0; i < 8; ++i) x[i] = xin[i] * s;
   typename O::vec b[3];
   O::split(x, b);
-  typename O::vec are[3], aim[3];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    if (k < O::terms) {
-      are[k] = O::load(amat + ((size_t)(0 * kMfmaTerms + k) * 64 + lane) * 8);
-      aim[k] = O::load(amat + ((size_t)(1 * kMfmaTerms + k) * 64 + lane) * 8);
-    } else {
-      are[k] = aim[k] = typename O::vec{};
-    }
-  }
   const float4_t dre = O::product(are, b);
   const float4_t dim = O::product(aim, b);
 #pragma unroll
@@ -151,14 +169,13 @@ __device__ __forceinline__ void dft16_mfma(const float (&xin)[8], const uint16_t
 
 // 256-point FFTs (sign +) of 16 transforms held in LDS, natural order, transform t at x + t * xstride
 // (complex64).  ys: LDS scratch of 2 * 16 * kYStride floats.  Wave w computes butterflies j = 4 w .. 4 w + 3 of
-// each stage.  out(t, q, value) receives output q of transform t in the lane that computed it (each (t, q) once).
-// Contains one barrier; the caller synchronises before x is reused.
+// each stage.  out(t, q, value, jj, i) receives output q of transform t in the lane that computed it (each
+// (t, q) once).  Contains one barrier; the caller synchronises before x is reused.
 template <bool BF16, class Out>
-__device__ __forceinline__ void fft256x16_mfma(const float2 *x, int xstride, float *ys,
-                                               const uint16_t *__restrict__ table, Out out) {
+__device__ __forceinline__ void fft256x16_mfma(const float2 *x, int xstride, float *ys, const MfmaMats<BF16> &M,
+                                               Out out) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int t = lane & 15, g = lane >> 4, comp = g >> 1, half = g & 1;
-  constexpr size_t kMat = (size_t)2 * kMfmaTerms * 64 * 8;   // halfs per matrix
   const float *xf = reinterpret_cast<const float *>(x);
   // stage 1: butterfly j takes x[j + 16 m]
 #pragma unroll
@@ -168,7 +185,7 @@ __device__ __forceinline__ void fft256x16_mfma(const float2 *x, int xstride, flo
 #pragma unroll
     for (int i = 0; i < 8; ++i) v[i] = xf[2 * (t * xstride + j + 16 * (8 * half + i)) + comp];
     float yre[4], yim[4];
-    dft16_mfma<BF16>(v, table, lane, yre, yim);
+    dft16_mfma<BF16>(v, M.s1[0], M.s1[1], yre, yim);
     // stage-1 output (j, r) goes to ys[c][t][r][j]
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -189,7 +206,7 @@ __device__ __forceinline__ void fft256x16_mfma(const float2 *x, int xstride, flo
     v[0] = a0.x; v[1] = a0.y; v[2] = a0.z; v[3] = a0.w;
     v[4] = a1.x; v[5] = a1.y; v[6] = a1.z; v[7] = a1.w;
     float yre[4], yim[4];
-    dft16_mfma<BF16>(v, table + (size_t)(1 + j2) * kMat, lane, yre, yim);
+    dft16_mfma<BF16>(v, M.s2[jj][0], M.s2[jj][1], yre, yim);
 #pragma unroll
     for (int i = 0; i < 4; ++i) out(t, j2 + 16 * (4 * g + i), make_float2(yre[i], yim[i]), jj, i);
   }

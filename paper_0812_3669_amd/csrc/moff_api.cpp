@@ -56,6 +56,8 @@ moff_status need_bound(const moff::Plan &p, bool kernels) {
   return MOFF_OK;
 }
 
+bool is_jones(const moff::Plan &p) { return p.kernel_mode == MOFF_KERNEL_JONES; }
+
 moff::RowArgs row_args(const moff::Plan &p, const void *volt) {
   moff::RowArgs a{};
   a.bands = d_bands(p);
@@ -110,6 +112,7 @@ int band_count(const moff::Plan &p, const moff::Block &b) {
 
 moff_status enqueue_correlate(moff::Plan &p, const void *d_volt, int64_t n_t, void *d_acc, hipStream_t st) {
   float2 *H = reinterpret_cast<float2 *>(ws(p, p.ws_h));
+  const bool jones = is_jones(p);
   moff::RowArgs a = row_args(p, d_volt);
   a.io = H;
   moff::ColArgs ca{};
@@ -139,7 +142,7 @@ moff_status enqueue_correlate(moff::Plan &p, const void *d_volt, int64_t n_t, vo
         if (split)
           HIP_TRY(moff::launch_rows_mfma(bf16, a, mtab, rgrid, st), "row pass");
         else
-          HIP_TRY(moff::launch_rows(b.n, p.n_pol, moff::ROW_MODE_FUSED, a, rgrid, lds, st), "row pass");
+          HIP_TRY(moff::launch_rows(b.n, p.n_pol, moff::ROW_MODE_FUSED, jones, a, rgrid, lds, st), "row pass");
         HIP_TRY(ps.done(), "profile event");
       }
       const int W = p.chans[b.c0].cols;
@@ -287,19 +290,23 @@ moff_status moff_bind(moff_plan_t plan, void *d_ws, size_t bytes, void *stream) 
   return ok();
 }
 
-moff_status moff_set_kernels(moff_plan_t plan, const void *d_kern, void *stream) {
+moff_status moff_set_kernels_phased(moff_plan_t plan, const void *d_kern, const void *d_phase, void *stream) {
   if (!plan || !d_kern) return set_err(MOFF_E_INVALID, "null argument");
   moff::Plan &p = plan->p;
   moff_status s = need_bound(p, false);
   if (s) return s;
-  HIP_TRY(moff::launch_pack_kernels(static_cast<const float2 *>(d_kern),
+  HIP_TRY(moff::launch_pack_kernels(static_cast<const float2 *>(d_kern), static_cast<const float2 *>(d_phase),
                                     reinterpret_cast<const int32_t *>(ws(p, p.ws_kidx)),
                                     reinterpret_cast<const int32_t *>(ws(p, p.ws_gchan)),
                                     reinterpret_cast<float2 *>(ws(p, p.ws_wk)), p.n_groups, p.n_ant, p.n_pol,
-                                    p.ksize * p.ksize, static_cast<hipStream_t>(stream)),
+                                    p.ksize * p.ksize, p.kplanes(), static_cast<hipStream_t>(stream)),
           "pack kernels");
   p.kernels_set = true;
   return ok();
+}
+
+moff_status moff_set_kernels(moff_plan_t plan, const void *d_kern, void *stream) {
+  return moff_set_kernels_phased(plan, d_kern, nullptr, stream);
 }
 
 moff_status moff_grid(moff_plan_t plan, const void *d_volt, int64_t n_t, void *d_grid, void *stream) {
@@ -313,6 +320,7 @@ moff_status moff_grid(moff_plan_t plan, const void *d_volt, int64_t n_t, void *d
   if (n_t > INT32_MAX / 2) return set_err(MOFF_E_INVALID, "n_t too large for one call");
   hipStream_t st = static_cast<hipStream_t>(stream);
   HIP_TRY(moff::launch_fill_zero(d_grid, (size_t)n_t * p.n_pol * p.pix_total * 8, st), "clear grid");
+  const bool jones = is_jones(p);
   moff::RowArgs a = row_args(p, d_volt);
   a.io = static_cast<float2 *>(d_grid);
   a.t0 = 0;
@@ -324,7 +332,7 @@ moff_status moff_grid(moff_plan_t plan, const void *d_volt, int64_t n_t, void *d
     a.tw = d_tw(p, b.n);
     const int tgroups = (int)((n_t + p.t_group - 1) / p.t_group);
     const size_t lds = moff::rows_lds_bytes(b.n, p.n_pol, p.chans[b.c0].band_rows, p.n_ant, p.volt_format);
-    HIP_TRY(moff::launch_rows(b.n, p.n_pol, moff::ROW_MODE_GRID, a, a.n_bands * tgroups, lds, st), "grid");
+    HIP_TRY(moff::launch_rows(b.n, p.n_pol, moff::ROW_MODE_GRID, jones, a, a.n_bands * tgroups, lds, st), "grid");
   }
   return ok();
 }
@@ -358,7 +366,7 @@ moff_status moff_fft(moff_plan_t plan, void *d_grid, int64_t n_t, void *stream) 
     a.tw = d_tw(p, b.n);
     const int tgroups = (int)((n_t + p.t_group - 1) / p.t_group);
     const size_t lds = moff::rows_lds_bytes(b.n, p.n_pol, p.chans[b.c0].band_rows, p.n_ant, p.volt_format);
-    HIP_TRY(moff::launch_rows(b.n, p.n_pol, moff::ROW_MODE_FFT, a, a.n_bands * tgroups, lds, st), "row fft");
+    HIP_TRY(moff::launch_rows(b.n, p.n_pol, moff::ROW_MODE_FFT, false, a, a.n_bands * tgroups, lds, st), "row fft");
   }
   for (const moff::Block &b : p.blocks) {
     const int W = p.chans[b.c0].cols;

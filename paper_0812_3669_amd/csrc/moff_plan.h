@@ -47,7 +47,7 @@ struct Plan {
   // description (copied)
   int32_t n_ant = 0, n_pol = 0, n_chan = 0, ksize = 0;
   double cell_lambda = 1.0;
-  int32_t fft_mode = 0, acc_mode = 0, time_block = 0, volt_format = 0;
+  int32_t fft_mode = 0, acc_mode = 0, time_block = 0, volt_format = 0, kernel_mode = 0;
   std::vector<double> ant_xy, freq;
 
   // geometry
@@ -105,6 +105,7 @@ struct Plan {
   size_t ev_used = 0;
 
   int n_prod() const { return n_pol == 2 ? 4 : 1; }
+  int kplanes() const { return kernel_mode == MOFF_KERNEL_JONES ? 4 : n_pol; }   // packed kernel planes
   int acc_reals() const { return n_pol == 2 ? 4 : 1; }
   size_t acc_elem_bytes() const { return acc_mode == MOFF_ACC_FP64_COMP ? 16 : 4; }
   size_t volt_sample_bytes() const {  // one time sample, all channels

@@ -75,6 +75,12 @@ moff_status build_plan(const moff_plan_desc &d, Plan &p, std::string *err) {
   if (d.volt_format != MOFF_VOLT_INT8 && d.volt_format != MOFF_VOLT_C64)
     return fail(err, MOFF_E_INVALID, "unknown volt_format");
   if (d.time_block < 0) return fail(err, MOFF_E_INVALID, "time_block must be >= 0");
+  if (d.kernel_mode != MOFF_KERNEL_DIAG && d.kernel_mode != MOFF_KERNEL_JONES)
+    return fail(err, MOFF_E_INVALID, "unknown kernel_mode");
+  if (d.kernel_mode == MOFF_KERNEL_JONES && d.n_pol != 2)
+    return fail(err, MOFF_E_INVALID, "Jones kernels need two pols");
+  if (d.kernel_mode == MOFF_KERNEL_JONES && d.fft_mode != MOFF_FFT_FP32)
+    return fail(err, MOFF_E_UNSUPPORTED, "Jones kernels are built for the FP32 transform");
 
   p.n_ant = d.n_ant;
   p.n_pol = d.n_pol;
@@ -84,6 +90,7 @@ moff_status build_plan(const moff_plan_desc &d, Plan &p, std::string *err) {
   p.fft_mode = d.fft_mode;
   p.acc_mode = d.acc_mode;
   p.volt_format = d.volt_format;
+  p.kernel_mode = d.kernel_mode;
   p.ant_xy.assign(d.ant_xy_m, d.ant_xy_m + 2 * (size_t)d.n_ant);
   p.freq.assign(d.freq_hz, d.freq_hz + d.n_chan);
   for (double v : p.ant_xy)
@@ -94,9 +101,10 @@ moff_status build_plan(const moff_plan_desc &d, Plan &p, std::string *err) {
   const int A = p.n_ant, C = p.n_chan, K = p.ksize, P = p.n_pol;
   // launch-block shape of the fused path (defaults; MOFF_T_BLOCK, MOFF_T_GROUP, MOFF_CHANS_PER_BLOCK override)
   if (d.chans_per_block < 0 || d.time_group < 0) return fail(err, MOFF_E_INVALID, "launch shape must be >= 0");
-  const int tb = d.time_block > 0 ? d.time_block : env_int("MOFF_T_BLOCK", 16, 1, 4096);
+  // defaults: the shape the autotuner picks for the 2048-antenna, 256^2 workload on MI355X
+  const int tb = d.time_block > 0 ? d.time_block : env_int("MOFF_T_BLOCK", 64, 1, 4096);
   const int tg = d.time_group > 0 ? d.time_group : env_int("MOFF_T_GROUP", 4, 1, 4096);
-  const int cpb = d.chans_per_block > 0 ? d.chans_per_block : env_int("MOFF_CHANS_PER_BLOCK", 16, 1, 1 << 20);
+  const int cpb = d.chans_per_block > 0 ? d.chans_per_block : env_int("MOFF_CHANS_PER_BLOCK", 64, 1, 1 << 20);
 
   // ---- per-channel grid size and footprints ------------------------------------------------------------
   p.chans.assign(C, Chan{});
@@ -263,7 +271,7 @@ moff_status build_plan(const moff_plan_desc &d, Plan &p, std::string *err) {
   p.ws_gchan = off;
   off = align256(off + p.grp_chan.size() * 4);
   p.ws_wk = off;
-  off = align256(off + (size_t)p.n_groups * P * kGroupLanes * 8);
+  off = align256(off + (size_t)p.n_groups * p.kplanes() * kGroupLanes * 8);
   p.ws_mfma = off;
   if (p.fft_mode != MOFF_FFT_FP32) off = align256(off + kMfmaTableBytesHost);
   p.ws_h = off;

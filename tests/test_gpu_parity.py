@@ -286,3 +286,110 @@ def test_split_precision_transform(mode, acc_mode):
     ref = ora.image(volts, kern, geo.ant_xy_m, geo.freqs_hz, geo.grid_n, cfg.cell_lambda)
     worst = _check_images(imgs, ref, label=f"split mode {mode}")
     print(f"split mode {mode} acc {acc_mode}: worst per-image error {worst:.2e}")
+
+
+# ---------------------------------------------------------------------------------------------------------
+# the headline workload at full size, in the launch configuration the benchmark times
+# ---------------------------------------------------------------------------------------------------------
+def test_headline_full_size_sampled_pixels():
+    """2048 antennas, 128 channels, 256^2, all 16384 samples (device-drawn int8 voltages), default launch shape,
+    graph replay.  Sampled pixels of the lowest and highest channel against the oracle evaluated pixel by
+    pixel over the whole integration.  Scale per product: the largest |oracle| over the sampled pixels, which
+    include the centre pixel (the autocorrelation peak)."""
+    cfg = configs.HEADLINE
+    geo = synth.geometry(cfg)
+    g = synth.gains(cfg)
+    sk = synth.sky(cfg)
+    kern = synth.kernels(geo, g, cfg.n_pol)
+    dev = torch.device(DEV)
+    volts = synth.DeviceVoltages(cfg, geo, g, sk, dev, chunk=64).all(cfg.n_time)
+    plan = api.plan_for(cfg, geo).bind(dev)
+    plan.set_kernels(torch.from_numpy(kern).to(dev))
+    acc = plan.new_accumulator()
+    plan.correlate_graph(volts, acc)
+    imgs = plan.read_image(acc)
+    n = cfg.grid_n
+    pix = np.array([[n // 2, n // 2], [n // 2 + 1, n // 2], [3, 250], [200, 17], [128, 77], [255, 0]])
+    for c in (0, cfg.n_chan - 1):
+        got = imgs[c].cpu().numpy()[:, pix[:, 0], pix[:, 1]].astype(np.complex128)
+        v = volts[:, c:c + 1].cpu().numpy()
+        ref = ora.image_pixels(v, kern[c], geo.ant_xy_m, geo.freqs_hz[c], n, cfg.cell_lambda, pix, t_batch=512)
+        sxx, syy = np.abs(ref[0]).max(), np.abs(ref[1]).max()
+        scale = np.array([sxx, syy, np.sqrt(sxx * syy), np.sqrt(sxx * syy)])[:, None]
+        err = (np.abs(got - ref) / scale).max(axis=1)
+        assert np.all(err <= TOL), (c, err)
+
+
+# ---------------------------------------------------------------------------------------------------------
+# phase-centre tracking and full-polarisation (Jones) kernels
+# ---------------------------------------------------------------------------------------------------------
+def _phases(cfg, seed):
+    rng = np.random.default_rng(seed)
+    return np.exp(2j * np.pi * rng.random((cfg.n_chan, cfg.n_ant, cfg.n_pol))).astype(np.complex64)
+
+
+def test_phase_tracking_per_time_block():
+    """Each antenna's voltage times a phase before gridding, the phases changing between two blocks of samples;
+    then back to no phase.  Against the oracle on the phased voltages."""
+    cfg = _small(128, C=2, A=48, T=14, seed=7)
+    geo, kern, volts, plan = _setup(cfg)
+    ph1, ph2 = _phases(cfg, 1), _phases(cfg, 2)
+    kd = torch.from_numpy(np.ascontiguousarray(kern)).to(DEV)
+    v = torch.from_numpy(volts).to(DEV)
+    acc = plan.new_accumulator()
+    plan.set_kernels(kd, phase=torch.from_numpy(ph1).to(DEV))
+    plan.correlate(v[:6].contiguous(), acc)
+    plan.set_kernels(kd, phase=torch.from_numpy(ph2).to(DEV))
+    plan.correlate(v[6:].contiguous(), acc)
+    imgs = [im.cpu().numpy().astype(np.complex128) for im in plan.read_image(acc)]
+    args = (kern, geo.ant_xy_m, geo.freqs_hz, geo.grid_n, cfg.cell_lambda)
+    r1 = ora.image(ora.apply_phases(volts[:6], ph1), *args)
+    r2 = ora.image(ora.apply_phases(volts[6:], ph2), *args)
+    _check_images(imgs, [a + b for a, b in zip(r1, r2)], label="phased")
+    plan.set_kernels(kd)
+    imgs, _ = _run_fused(plan, volts)
+    _check_images(imgs, ora.image(volts, *args), label="unphased again")
+
+
+def _jones_kernels(kern, seed, leak=0.3):
+    """Diagonal kernels [C, A, 2, K, K] plus random off-diagonal leakage -> [C, A, 2, 2, K, K]."""
+    rng = np.random.default_rng(seed)
+    C, A, P, K, _ = kern.shape
+    J = np.zeros((C, A, 2, 2, K, K), dtype=np.complex64)
+    for p in range(2):
+        J[:, :, p, p] = kern[:, :, p]
+        q = 1 - p
+        J[:, :, p, q] = leak * (rng.standard_normal((C, A, K, K)) + 1j * rng.standard_normal((C, A, K, K)))
+    return J
+
+
+@pytest.mark.parametrize("n,K,A,C,T,tb", [(64, 4, 40, 2, 9, 0), (128, 6, 61, 2, 13, 4), (256, 4, 75, 1, 5, 0)])
+def test_jones_kernels_fused(n, K, A, C, T, tb):
+    cfg = _small(n, A=A, C=C, T=T, K=K, seed=20 + n)
+    geo, kern, volts = synth.workload(cfg)
+    J = _jones_kernels(kern, seed=n)
+    plan = api.plan_for(cfg, geo, kernel_mode=api.KERNEL_JONES, time_block=tb).bind(DEV)
+    plan.set_kernels(torch.from_numpy(J).to(DEV))
+    imgs, _ = _run_fused(plan, volts)
+    ref = ora.image_jones(volts, J, geo.ant_xy_m, geo.freqs_hz, geo.grid_n, cfg.cell_lambda)
+    _check_images(imgs, ref, label=f"jones n={n}")
+
+
+def test_jones_staged_grid_and_phase():
+    """Staged gridding with Jones kernels (both pols into each grid), with phases folded in."""
+    cfg = _small(64, A=33, C=2, T=4, seed=31)
+    geo, kern, volts = synth.workload(cfg)
+    J = _jones_kernels(kern, seed=5)
+    ph = _phases(cfg, 9)
+    plan = api.plan_for(cfg, geo, kernel_mode=api.KERNEL_JONES).bind(DEV)
+    plan.set_kernels(torch.from_numpy(J).to(DEV), phase=torch.from_numpy(ph).to(DEV))
+    g = plan.grid(torch.from_numpy(volts).to(DEV))
+    grids = [x.cpu().numpy() for x in plan.split_grids(g, cfg.n_time)]
+    e = ora.apply_phases(volts, ph)
+    n = cfg.grid_n
+    for c in range(cfg.n_chan):
+        origin = ora.footprint_origin(geo.ant_xy_m, geo.freqs_hz[c], cfg.cell_lambda, n, cfg.ksize)
+        for p in range(2):
+            ref = sum(ora.grid_many(e[:, c, :, q], J[c, :, p, q], origin, n) for q in range(2))
+            err = np.abs(grids[c][:, p] - ref).max() / np.abs(ref).max()
+            assert err < 1e-6, (c, p, err)

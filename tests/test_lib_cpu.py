@@ -73,6 +73,8 @@ def test_boundary_antennas_listed_in_both_bands():
 @pytest.mark.parametrize("kw,status", [
     (dict(ksize=3), 1), (dict(ksize=10), 1), (dict(n_pol=3), 1), (dict(grid_n=[48]), 4),
     (dict(grid_n=[16]), 4), (dict(cell_lambda=0.0), 1), (dict(fft_mode=7), 1), (dict(acc_mode=5), 1),
+    (dict(kernel_mode=2), 1), (dict(kernel_mode=1, n_pol=1), 1),
+    (dict(kernel_mode=1, grid_n=[256], fft_mode=1), 4),
 ])
 def test_plan_validation(kw, status):
     xy = np.array([[1.0, 2.0], [-3.0, 4.0], [5.0, -6.0]])
@@ -135,3 +137,14 @@ def test_split_precision_transform_needs_256_grids_and_two_pols():
         assert ei.value.status == 4
     Plan(xy, [configs.C_LIGHT], [256], n_pol=2, ksize=4, fft_mode=1)
     Plan(xy, [configs.C_LIGHT], [256], n_pol=2, ksize=4, fft_mode=2)
+
+
+def test_jones_kernels_pack_four_planes():
+    xy = np.array([[1.0, 2.0], [-3.0, 4.0]])
+    diag = Plan(xy, [configs.C_LIGHT], [32], n_pol=2, ksize=4)
+    jones = Plan(xy, [configs.C_LIGHT], [32], n_pol=2, ksize=4, kernel_mode=1)
+    assert jones._kernel_shape() == (1, 2, 2, 2, 4, 4)
+    assert diag._kernel_shape() == (1, 2, 2, 4, 4)
+    # the packed kernel table doubles (four planes instead of two); nothing else in the workspace changes
+    assert jones.workspace_bytes > diag.workspace_bytes
+    assert jones.acc_bytes == diag.acc_bytes
