@@ -84,6 +84,36 @@ def cpu_baseline(cfg, geo, kern_np, volts_dev, budget_s: float = 12.0):
                       f"{t_used:.1f} s"}
 
 
+def serving_bench(args, dev):
+    """The serving trace: seeded Poisson arrivals (200 jobs/s), job shapes drawn from the serving sets,
+    integration lengths scaled by ``--time-scale``; p50/p99 latency (completion - arrival, queueing included)
+    beside aggregate channel-samples/s."""
+    import torch
+    from paper_0812_3669_amd import serve
+    trace = serve.make_trace(seed=4000, n_jobs=args.jobs, rate=200.0, time_scale=args.time_scale)
+    free, total = torch.cuda.mem_get_info(dev)
+    budget = int(0.8 * free)
+    ex = serve.GpuExecutor(dev)
+    sch = serve.Scheduler(ex, hbm_budget=budget, max_slots=8, block=64)
+    print(f"bench: serving {len(trace)} jobs, HBM budget {budget / 2**30:.1f} GiB", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    st = sch.run(trace, realtime=True)
+    torch.cuda.synchronize()
+    summ = st.summary()
+    out = {
+        "metric": "p99 job latency, serving trace (continuous batching, HBM-budget admission)",
+        "value": summ["p99_latency_s"], "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": summ["wall_s"] * 1e3, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 / f16x2->f32 per job", "data": "synthetic (seeded point sources + noise, int8 voltages)",
+        "config": {"workload": "serving: Poisson 200 jobs/s, %d jobs, antennas {256,1024,4096,8192}, channels "
+                               "{16,64,256}, samples {1k,8k,64k} x %.4g, grids {128,256,512}, fp32 or "
+                               "split_fp16 (256^2 grids), 64-sample blocks, 8 slots" % (len(trace), args.time_scale),
+                   "hbm_budget_bytes": budget},
+        "serving": summ,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +127,11 @@ def main():
     ap.add_argument("--autotune", action="store_true", help="tune the launch shape on the first 256 samples")
     ap.add_argument("--eager", action="store_true", help="launch kernel by kernel instead of replaying a HIP graph")
     ap.add_argument("--calibrate-copy", action="store_true", help="run a 1 GiB device copy (PMC calibration)")
+    ap.add_argument("--jobs", type=int, default=48, help="serving: jobs in the trace")
+    ap.add_argument("--time-scale", type=float, default=1.0 / 64, help="serving: integration-length factor")
+    ap.add_argument("--workload", choices=["headline", "batched", "serving"], default="headline",
+                    help="headline: 2048 antennas, 256^2 grids; batched: 4096 antennas, 256 channels over "
+                         "50-200 MHz with per-channel grid sizes (128^2..384^2), 6x6 kernels")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -118,7 +153,10 @@ def main():
         print(json.dumps({"calibrate_copy_bytes": a.numel() * 4, "launches": 3}))
         return
 
-    cfg = configs.HEADLINE
+    if args.workload == "serving":
+        serving_bench(args, dev)
+        return
+    cfg = configs.HEADLINE if args.workload == "headline" else configs.BATCHED
     T = args.time or cfg.n_time
     print(f"bench: building workload {cfg.name} (T={T})", file=sys.stderr, flush=True)
     geo = synth.geometry(cfg)
@@ -173,41 +211,55 @@ def main():
     value = cs / (ms / 1e3)
     print(f"bench: {ms:.2f} ms/step", file=sys.stderr, flush=True)
 
-    # per-kernel event timing over the timed steps
-    n, P, K, A = 256, cfg.n_pol, cfg.ksize, cfg.n_ant
-    flops = {0: 8.0 * A * P * K * K + 5.0 * n * n * math.log2(n) * P,        # gridding + row FFTs
-             1: 5.0 * n * n * math.log2(n) * P + 16.0 * n * n}             # column FFTs + products
+    # per-kernel event timing over the profiled step; algorithmic flops per channel-sample of each pass
+    P, K, A = cfg.n_pol, cfg.ksize, cfg.n_ant
+
+    def pass_flops(kind, n):
+        fft_half = 5.0 * n * n * math.log2(n) * P          # half of the 2-D transform (rows or columns)
+        return 8.0 * A * P * K * K + fft_half if kind == 0 else fft_half + 16.0 * n * n
+
     names = {0: "k_rows", 1: "k_cols"}
     kt = {}
     for kind in (0, 1):
         tot_ms, launches, kcs = plan.profile_read(kind)
-        kt[kind] = dict(ms=tot_ms, launches=launches, cs=kcs)
+        # the profiled step covers every channel for T samples; split its channel-samples by grid size
+        step_flops = sum(T * pass_flops(kind, n) for n in plan.grid_n)
+        kt[kind] = dict(ms=tot_ms, launches=launches, cs=kcs, flops=step_flops * kcs / (T * cfg.n_chan))
     dom = max(kt, key=lambda k: kt[k]["ms"])
     d = kt[dom]
     avg_ms = d["ms"] / max(d["launches"], 1)
-    per_launch_flops = flops[dom] * d["cs"] / max(d["launches"], 1)
+    per_launch_flops = d["flops"] / max(d["launches"], 1)
     achieved = per_launch_flops / (avg_ms / 1e3)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP32_VECTOR,
-                "traffic": _traffic(names[dom], round(d["cs"] / max(d["launches"], 1))),
+                "traffic": _traffic(names[dom], round(d["cs"] / max(d["launches"], 1)))
+                if args.workload == "headline" else None,
                 "kernel": names[dom], "avg_launch_ms": avg_ms,
                 "kernel_share": {names[k]: kt[k]["ms"] / (kt[0]["ms"] + kt[1]["ms"]) for k in kt}}
+    algo_flops_step = sum(T * cfg.flops_per_cs(n) for n in plan.grid_n)
+    if args.workload == "headline":
+        metric = "channel-samples imaged/s (N=2048, 256^2 grid), "
+        workload = ("headline: 2048 antennas, 200-lambda disk, 128 channels 100-130 MHz, 2 pols, 4x4 kernels, "
+                    "256^2 grid, %d samples, int8" % T)
+    else:
+        metric = "channel-samples imaged/s (N=4096, per-channel grids 128^2..384^2), "
+        sizes = sorted(set(plan.grid_n))
+        workload = ("batched: 4096 antennas, 376-lambda disk at 200 MHz, 256 channels 50-200 MHz, 2 pols, 6x6 "
+                    "kernels, per-channel grids %s, %d samples, int8" % ("/".join(map(str, sizes)), T))
 
     out = {
-        "metric": "channel-samples imaged/s (N=2048, 256^2 grid), " +
-                  ("plain FP32 path" if args.fft == "fp32" else f"{args.fft} matrix-core transform"),
+        "metric": metric + ("plain FP32 path" if args.fft == "fp32" else f"{args.fft} matrix-core transform"),
         "value": value, "unit": "channel-samples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": {"fp32": "f32", "split_fp16": "f16x2->f32", "split_bf16": "bf16x3->f32"}[args.fft],
         "data": "synthetic (seeded point sources + noise, int8 voltages)",
-        "config": {"workload": "headline: 2048 antennas, 200-lambda disk, 128 channels 100-130 MHz, 2 pols, "
-                               "4x4 kernels, 256^2 grid, 16384 samples, int8",
+        "config": {"workload": workload,
                    "channel_samples_per_step": cs, "accumulator": args.acc,
                    "fft": args.fft,
                    "launch_shape": dict(zip(("time_block", "chans_per_block", "time_group"), plan.launch_shape())),
                    "graph_replay": not args.eager,
-                   "algorithmic_flops_per_cs": cfg.flops_per_cs(),
-                   "achieved_algorithmic_tflops": value * cfg.flops_per_cs() / 1e12},
+                   "algorithmic_flops_per_cs": algo_flops_step / cs,
+                   "achieved_algorithmic_tflops": algo_flops_step / (ms / 1e3) / 1e12},
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:

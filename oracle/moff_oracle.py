@@ -103,7 +103,7 @@ def grid_many(e: np.ndarray, kern: np.ndarray, origin: np.ndarray, n: int) -> np
     cell = (np.broadcast_to(jj, (A, K, K)) * n + np.broadcast_to(ii, (A, K, K))).ravel()
     ant = np.broadcast_to(np.arange(A)[:, None, None], (A, K, K)).ravel()
     W = sp.csr_matrix((kern.astype(np.complex128).ravel(), (cell, ant)), shape=(n * n, A))
-    return np.asarray((W @ e.T).T).reshape(e.shape[0], n, n)
+    return np.ascontiguousarray(np.asarray((W @ e.T).T)).reshape(e.shape[0], n, n)
 
 
 # ---------------------------------------------------------------------------------------------------------

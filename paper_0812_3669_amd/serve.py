@@ -42,14 +42,31 @@ class JobSpec:
     mode: str = "fp32"
     seed: int = 0
 
-    def config(self) -> configs.Config:
-        """Workload of this job: band 100-130 MHz, 4x4 kernels, the array disk filling the grid at the top
-        channel (diameter n - K - 2 wavelengths), int8 voltages, 5 point sources."""
+    def site_config(self) -> configs.Config:
+        """The array a job observes with: band 100-130 MHz, 4x4 kernels, the disk filling the grid at the top
+        channel (diameter n - K - 2 wavelengths), int8 voltages, 5 point sources.  Positions, gains and kernels
+        depend on the array shape (antennas, channels, grid) only, as an instrument's do; the sky and the
+        voltages come from ``config()``, which differs per job."""
         K = 4
-        return configs.Config(f"job{self.job_id}", 1000 + self.seed, n_ant=self.n_ant, n_pol=2,
-                              n_chan=self.n_chan, ksize=K, f_lo=100e6, f_hi=130e6,
-                              disk_lambda=float(self.grid_n - K - 2), disk_ref_hz=130e6, grid_n=self.grid_n,
-                              n_time=self.n_time, n_src=5)
+        site = 7919 * self.n_ant + 131 * self.n_chan + self.grid_n
+        return configs.Config(f"site{site}", 10_000 + site, n_ant=self.n_ant, n_pol=2, n_chan=self.n_chan,
+                              ksize=K, f_lo=100e6, f_hi=130e6, disk_lambda=float(self.grid_n - K - 2),
+                              disk_ref_hz=130e6, grid_n=self.grid_n, n_time=self.n_time, n_src=5)
+
+    def config(self) -> configs.Config:
+        """The job's own seeds (sky and voltages), same shapes as ``site_config``."""
+        return configs.scaled(self.site_config(), name=f"job{self.job_id}", index=1000 + self.seed)
+
+    @property
+    def fft_mode(self) -> str:
+        """The split-precision transform is built for 256^2 grids; other sizes run the FP32 transform."""
+        return self.mode if self.grid_n == 256 else "fp32"
+
+    def chans_per_launch(self, block: int, cap_bytes: int = 1 << 30) -> int:
+        """Channels per launch so that the row-transform buffer (block samples x channels x 2 pols x n^2 x 8 B)
+        stays under ``cap_bytes``: concurrent jobs then leave room for each other."""
+        per = block * 2 * self.grid_n ** 2 * 8
+        return int(max(1, min(self.n_chan, 64, cap_bytes // per)))
 
     @property
     def channel_samples(self) -> int:
@@ -144,6 +161,8 @@ class Scheduler:
                 need = self.ex.hbm(spec, self.block)
                 if need > self.budget:
                     st.rejected += 1          # can never fit: reject at once
+                    if hasattr(self.ex, "discard"):
+                        self.ex.discard(spec)
                     continue
                 queue.append(spec)
             # admit in arrival order while a slot and memory are free
@@ -225,12 +244,19 @@ class ModelExecutor:
 
 
 class GpuExecutor:
-    """Runs each job through the C ABI on its own stream; voltages are drawn per block on the device."""
+    """Runs each job through the C ABI on its own stream; voltages are drawn per block on the device.
 
-    def __init__(self, device="cuda:0"):
+    ``hbm`` builds the job's plan (host only) the first time it is asked, so admission uses the exact device
+    footprint: plan workspace + accumulator + image + kernels + one block of voltages.  Kernels are cached on
+    the device per array shape while a job of that shape is active.
+    """
+
+    def __init__(self, device="cuda:0", keep_plans: int = 64):
         import torch
         self.torch = torch
         self.device = torch.device(device)
+        self._plans = {}
+        self._sites = {}
 
     def now(self):
         return time.perf_counter()
@@ -241,27 +267,55 @@ class GpuExecutor:
     def advance_to(self, t):
         self.sleep(t - self.now())
 
+    def _site(self, spec):
+        from . import synth
+        key = (spec.n_ant, spec.n_chan, spec.grid_n)
+        if key not in self._sites:
+            scfg = spec.site_config()
+            geo = synth.geometry(scfg)
+            g = synth.gains(scfg)
+            self._sites[key] = {"geo": geo, "g": g, "kern_np": synth.kernels(geo, g, 2), "kern": None, "users": 0}
+        return self._sites[key]
+
+    def _plan(self, spec, block):
+        from . import api
+        if spec.job_id not in self._plans:
+            site = self._site(spec)
+            fft = {"fp32": api.FFT_FP32, "split_fp16": api.FFT_SPLIT_FP16}[spec.fft_mode]
+            plan = api.plan_for(spec.site_config(), site["geo"], fft_mode=fft, time_block=block,
+                                chans_per_block=spec.chans_per_launch(block))
+            self._plans[spec.job_id] = plan
+        return self._plans[spec.job_id]
+
     def hbm(self, spec, block):
-        return hbm_bytes(spec, block)
+        plan = self._plan(spec, block)
+        kern = spec.n_chan * spec.n_ant * 2 * 16 * 8
+        volt = block * spec.n_chan * spec.n_ant * 2 * 2
+        return int(plan.workspace_bytes + plan.acc_bytes + plan.image_bytes + kern + volt)
+
+    def discard(self, spec):
+        self._plans.pop(spec.job_id, None)
 
     def start(self, spec, block):
-        from . import api, synth
+        from . import synth
         torch = self.torch
+        site = self._site(spec)
+        plan = self._plan(spec, block)
         cfg = spec.config()
-        geo = synth.geometry(cfg)
-        g = synth.gains(cfg)
         sk = synth.sky(cfg)
         stream = torch.cuda.Stream(device=self.device)
         with torch.cuda.stream(stream):
-            plan = api.plan_for(cfg, geo).bind(self.device, stream=stream)
-            kern = torch.from_numpy(synth.kernels(geo, g, cfg.n_pol)).to(self.device)
-            plan.set_kernels(kern, stream=stream)
+            if site["kern"] is None:
+                site["kern"] = torch.from_numpy(site["kern_np"]).to(self.device)
+            site["users"] += 1
+            plan.bind(self.device, stream=stream)
+            plan.set_kernels(site["kern"], stream=stream)
             acc = plan.new_accumulator()
-            gen = synth.DeviceVoltages(cfg, geo, g, sk, self.device, chunk=block)
+            gen = synth.DeviceVoltages(cfg, site["geo"], site["g"], sk, self.device, chunk=block)
             vbuf = torch.empty((block, cfg.n_chan, cfg.n_ant, cfg.n_pol, 2), dtype=torch.int8, device=self.device)
         ev = torch.cuda.Event()
         return {"spec": spec, "plan": plan, "acc": acc, "gen": gen, "vbuf": vbuf, "stream": stream, "ev": ev,
-                "kern": kern, "block": block}
+                "site": site, "block": block}
 
     def step(self, h, t0, nt):
         torch = self.torch
@@ -280,4 +334,9 @@ class GpuExecutor:
         with torch.cuda.stream(h["stream"]):
             img = h["plan"].read_image(h["acc"], n_samples=h["spec"].n_time, stream=h["stream"], split=False)
         h["stream"].synchronize()
+        site = h["site"]
+        site["users"] -= 1
+        if site["users"] == 0:
+            site["kern"] = None                 # free the device copy; the host copy stays cached
+        self._plans.pop(h["spec"].job_id, None)
         return img

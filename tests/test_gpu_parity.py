@@ -393,3 +393,28 @@ def test_jones_staged_grid_and_phase():
             ref = sum(ora.grid_many(e[:, c, :, q], J[c, :, p, q], origin, n) for q in range(2))
             err = np.abs(grids[c][:, p] - ref).max() / np.abs(ref).max()
             assert err < 1e-6, (c, p, err)
+
+
+def test_batched_workload_three_channels():
+    """The batching workload at full size (4096 antennas, 256 channels over 50-200 MHz, per-channel grids,
+    6x6 kernels) for 256 device-drawn samples through one graph-replayed correlate; the lowest, a middle and
+    the highest channel (smallest, middle and largest grid) checked pixel by pixel against the oracle."""
+    cfg = configs.scaled(configs.BATCHED, n_time=256)
+    geo = synth.geometry(cfg)
+    g = synth.gains(cfg)
+    sk = synth.sky(cfg)
+    kern = synth.kernels(geo, g, cfg.n_pol)
+    dev = torch.device(DEV)
+    volts = synth.DeviceVoltages(cfg, geo, g, sk, dev, chunk=64).all(cfg.n_time)
+    plan = api.plan_for(cfg, geo).bind(dev)
+    plan.set_kernels(torch.from_numpy(kern).to(dev))
+    acc = plan.new_accumulator()
+    plan.correlate_graph(volts, acc)
+    imgs = plan.read_image(acc)
+    sizes = plan.grid_n
+    mid = min(range(cfg.n_chan), key=lambda c: abs(sizes[c] - sorted(set(sizes))[len(set(sizes)) // 2]))
+    sel = [0, mid, cfg.n_chan - 1]
+    assert sizes[0] < sizes[mid] < sizes[-1], (sizes[0], sizes[mid], sizes[-1])
+    v = volts[:, sel].cpu().numpy()
+    ref = ora.image(v, kern[sel], geo.ant_xy_m, geo.freqs_hz[sel], geo.grid_n[sel], cfg.cell_lambda)
+    _check_images([imgs[c].cpu().numpy().astype(np.complex128) for c in sel], ref, label="batched")

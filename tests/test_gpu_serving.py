@@ -1,0 +1,63 @@
+"""Serving form on the GPU: jobs admitted by HBM budget, overlapping on their own streams; each job's image is
+the same alone and in a mix (bit for bit), and a small job matches the oracle."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import moff_oracle as ora
+from paper_0812_3669_amd import serve, synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+TOL = 1e-5
+
+JOBS = [
+    serve.JobSpec(0, 0.0, 256, 16, 128, 128, "fp32", seed=11),
+    serve.JobSpec(1, 0.0, 256, 16, 96, 256, "split_fp16", seed=12),
+    serve.JobSpec(2, 0.0, 1024, 16, 64, 128, "fp32", seed=13),
+]
+OTHERS = [
+    serve.JobSpec(3, 0.0, 1024, 64, 192, 256, "fp32", seed=14),
+    serve.JobSpec(4, 0.001, 256, 64, 128, 512, "fp32", seed=15),
+    serve.JobSpec(5, 0.002, 4096, 16, 64, 256, "split_fp16", seed=16),
+]
+
+
+def _run(trace, slots):
+    ex = serve.GpuExecutor(DEV)
+    sch = serve.Scheduler(ex, hbm_budget=64 << 30, max_slots=slots, block=64, keep_results=True)
+    st = sch.run(trace, realtime=False)
+    torch.cuda.synchronize()
+    return st
+
+
+def test_each_job_same_alone_and_in_the_mix():
+    alone = {}
+    for j in JOBS:
+        st = _run([j], 1)
+        alone[j.job_id] = st.results[j.job_id].cpu()
+    mix = JOBS + OTHERS
+    st = _run(mix, 4)
+    assert st.peak_concurrent >= 3, st.summary()
+    assert len(st.latencies) == len(mix)
+    for j in JOBS:
+        assert torch.equal(alone[j.job_id], st.results[j.job_id].cpu()), j
+
+
+def test_small_job_against_oracle():
+    j = JOBS[0]
+    st = _run([j], 1)
+    img = st.results[j.job_id].cpu().numpy().astype(np.complex128)
+    cfg, scfg = j.config(), j.site_config()
+    geo = synth.geometry(scfg)
+    g = synth.gains(scfg)
+    kern = synth.kernels(geo, g, 2)
+    volts = synth.DeviceVoltages(cfg, geo, g, synth.sky(cfg), torch.device(DEV), chunk=64).all(j.n_time)
+    n = j.grid_n
+    sel = [0, j.n_chan - 1]
+    ref = ora.image(volts[:, sel].cpu().numpy(), kern[sel], geo.ant_xy_m, geo.freqs_hz[sel], geo.grid_n[sel],
+                    scfg.cell_lambda)
+    for k, c in enumerate(sel):
+        got = img[c * 4 * n * n:(c + 1) * 4 * n * n].reshape(4, n, n)
+        e = ora.relative_errors(got, ref[k])
+        assert np.all(e <= TOL), (c, e)

@@ -2,6 +2,7 @@
 queueing, rejection of jobs that can never fit, latency accounting."""
 import numpy as np
 
+from paper_0812_3669_amd import serve
 from paper_0812_3669_amd.serve import JobSpec, ModelExecutor, Scheduler, hbm_bytes, make_trace
 
 
@@ -50,3 +51,15 @@ def test_arrivals_in_the_future_wait_for_their_time():
     assert st.summary()["jobs_completed"] == 3
     assert st.wall >= 10.0
     assert max(st.latencies) < 0.01
+
+
+def test_job_site_shared_by_shape_and_launch_cap():
+    a = serve.JobSpec(0, 0.0, 1024, 64, 128, 256, "split_fp16", seed=1)
+    b = serve.JobSpec(1, 0.5, 1024, 64, 4096, 256, "fp32", seed=2)
+    assert a.site_config().index == b.site_config().index          # same instrument
+    assert a.config().index != b.config().index                    # own sky and voltages
+    assert a.config().n_ant == a.site_config().n_ant and a.config().grid_n == 256
+    big = serve.JobSpec(2, 0.0, 8192, 256, 1024, 512, "split_fp16")
+    assert big.fft_mode == "fp32" and a.fft_mode == "split_fp16"
+    cpl = big.chans_per_launch(64)
+    assert cpl >= 1 and 64 * cpl * 2 * 512 ** 2 * 8 <= (1 << 30)
