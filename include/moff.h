@@ -69,6 +69,7 @@ typedef enum { MOFF_VOLT_INT8 = 0, MOFF_VOLT_C64 = 1 } moff_volt_format;
 /* Diagonal kernels: the X grid receives only X voltages (through K_{a,X}) and the Y grid only Y voltages.
  * Jones kernels (full polarimetry): grid p receives both pols of every antenna, G_p = sum_q K_{a,pq} E_{a,q}. */
 typedef enum { MOFF_KERNEL_DIAG = 0, MOFF_KERNEL_JONES = 1 } moff_kernel_mode;
+typedef enum { MOFF_PIPELINE_TWO_PASS = 0, MOFF_PIPELINE_STREAM = 1 } moff_pipeline;
 
 typedef struct {
   int32_t n_ant;            /* A >= 1 */
@@ -169,11 +170,29 @@ moff_status moff_autotune(moff_plan_t plan, const void *d_volt, int64_t n_t, voi
  * rebinding drops the cached graphs.  The buffers' contents may change between calls; their addresses may not. */
 moff_status moff_correlate_graph(moff_plan_t plan, const void *d_volt, int64_t n_t, void *d_acc, void *stream);
 
+/* How the fused path (moff_correlate, moff_correlate_graph) moves the row-transformed grids to the column pass
+ * -- the all-to-all of a 2-D FFT too large for one compute unit, which the paper's modular design does between
+ * spatial modules (Section 5).  MOFF_PIPELINE_TWO_PASS (default): a row-pass kernel writes them for a launch
+ * block of channels x samples and a column-pass kernel reads them back.  MOFF_PIPELINE_STREAM: one persistent
+ * launch per run of channels with one grid size; in each team of workgroups some own the column groups of a
+ * channel and keep transforming and accumulating while the others grid and row-transform the next samples into
+ * a small ring (device-coherent accesses, held by the memory-side cache), with counters ordering the two.
+ * Results equal the two-pass form's up to FP32 rounding (same sums, same accumulation blocks).  The streaming
+ * launch needs every workgroup resident: do not run other kernels concurrently on the device while it runs.
+ * Its waits are bounded (spin limit, MOFF_SPIN_LIMIT); a wait that times out ends the launch early and leaves a
+ * code that moff_stream_status reads (0 = fine; 1 = timed out, the accumulator is then not valid).
+ * MOFF_E_UNSUPPORTED for the split transforms.  Grid sizes whose kernel leaves too few resident workgroups for
+ * column owners plus row workers run two-pass within the same call.  Setting the pipeline drops cached graphs. */
+moff_status moff_set_pipeline(moff_plan_t plan, int32_t pipeline);
+/* Synchronises the device, then reads the streaming form's status code of the last fused call. */
+moff_status moff_stream_status(moff_plan_t plan, int32_t *code);
+
 /* Kernel timing (tracing).  moff_profile(plan, 1) starts recording a pair of HIP events around every launch of
  * the fused path on the caller's stream (earlier records are dropped); moff_profile(plan, 0) stops.  After the
- * stream has been synchronised, moff_profile_read sums, for kernel kind 0 (row pass: gridding + row FFTs) or
- * 1 (column pass: column FFTs + products + accumulation), the event-measured time in ms, the launch count and
- * the channel-samples those launches processed.  Recording adds two event records per launch. */
+ * stream has been synchronised, moff_profile_read sums, for kernel kind 0 (row pass: gridding + row FFTs),
+ * 1 (column pass: column FFTs + products + accumulation) or 2 (streaming form: both), the event-measured time
+ * in ms, the launch count and the channel-samples those launches processed.  Recording adds two event records
+ * per launch. */
 moff_status moff_profile(moff_plan_t plan, int32_t enable);
 moff_status moff_profile_read(moff_plan_t plan, int32_t kind, double *total_ms, int64_t *launches,
                               int64_t *channel_samples);

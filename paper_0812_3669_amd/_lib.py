@@ -14,6 +14,7 @@ FFT_FP32, FFT_SPLIT_FP16, FFT_SPLIT_BF16 = range(3)
 ACC_FP32, ACC_FP64_COMP = range(2)
 VOLT_INT8, VOLT_C64 = range(2)
 KERNEL_DIAG, KERNEL_JONES = range(2)
+PIPELINE_TWO_PASS, PIPELINE_STREAM = range(2)
 
 
 class PlanDesc(C.Structure):
@@ -37,6 +38,8 @@ _SIGS = {
     "moff_bind": ([_P, _P, C.c_size_t, _P], C.c_int),
     "moff_set_kernels": ([_P, _P, _P], C.c_int),
     "moff_set_kernels_phased": ([_P, _P, _P, _P], C.c_int),
+    "moff_set_pipeline": ([_P, C.c_int32], C.c_int),
+    "moff_stream_status": ([_P, C.POINTER(C.c_int32)], C.c_int),
     "moff_grid": ([_P, _P, C.c_int64, _P, _P], C.c_int),
     "moff_fft": ([_P, _P, C.c_int64, _P], C.c_int),
     "moff_accumulate": ([_P, _P, C.c_int64, _P, _P], C.c_int),

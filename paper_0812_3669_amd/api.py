@@ -16,7 +16,7 @@ import numpy as np
 
 from . import _lib
 from ._lib import (ACC_FP32, ACC_FP64_COMP, FFT_FP32, FFT_SPLIT_BF16, FFT_SPLIT_FP16,  # noqa: F401
-                   KERNEL_DIAG, KERNEL_JONES, VOLT_C64, VOLT_INT8)
+                   KERNEL_DIAG, KERNEL_JONES, PIPELINE_STREAM, PIPELINE_TWO_PASS, VOLT_C64, VOLT_INT8)
 
 
 class MoffError(RuntimeError):
@@ -177,6 +177,17 @@ class Plan:
         self._check_volts(volts, n_t)
         _check(self.lib.moff_correlate_graph(self._h, _ptr(volts), n_t, _ptr(acc), _stream_handle(stream)),
                "moff_correlate_graph")
+
+    def set_pipeline(self, pipeline: int):
+        """PIPELINE_TWO_PASS (row and column kernels) or PIPELINE_STREAM (one persistent launch per grid size)."""
+        _check(self.lib.moff_set_pipeline(self._h, int(pipeline)), "moff_set_pipeline")
+        return self
+
+    def stream_status(self) -> int:
+        """Status code of the streaming form's last call (0 = fine); synchronises the device."""
+        code = C.c_int32()
+        _check(self.lib.moff_stream_status(self._h, C.byref(code)), "moff_stream_status")
+        return code.value
 
     def launch_shape(self):
         tb, cpb, tg = C.c_int32(), C.c_int32(), C.c_int32()

@@ -60,7 +60,7 @@ struct ColArgs {
 // XCD-aware workgroup mapping of the fused passes.  Workgroups are dispatched round-robin over the 8 XCDs
 // (workgroup b runs on XCD b % 8), so channel c0 + k of a launch block is given to XCD k % 8: its tap tables and
 // voltages stay in one XCD's L2 instead of being fetched by all eight.  Padding workgroups get false.
-constexpr int kXcds = 8;
+constexpr int kXcds = kStreamXcds;
 
 __device__ inline bool rows_xcd_map(const RowArgs &a, int &band, int &tg) {
   const int x = (int)(blockIdx.x % kXcds), s = (int)(blockIdx.x / kXcds);
@@ -114,6 +114,36 @@ __device__ __forceinline__ float2 load_stream(const float2 *p) {
   return make_float2(v.x, v.y);
 }
 
+// Streaming form (one persistent launch per grid size; see k_stream).
+struct StreamArgs {
+  RowArgs r;                 // c0: first channel of the launch, t0 / nt: the samples
+  ColArgs c;                 // t_block: samples per accumulator update
+  float2 *ring;              // [kXcds][slots][P n^2] row-transformed samples in column-group tiles
+  uint32_t *ctr;             // [kXcds][2][slots] cumulative counters: bands produced, column groups consumed
+  int *err;                  // 0, or 1 (a wait timed out)
+  int slots;
+  int wgs_per_xcd;
+  int n_chan_group;          // channels c0 .. c0 + n_chan_group - 1, all of one grid size
+  uint32_t spin_limit;
+};
+
+// Device-coherent (agent scope) 8-byte store / load: not cached in the non-coherent L1 / L2, so a value
+// written by one workgroup is seen by another on any XCD once the writer's stores have completed.
+__device__ __forceinline__ void store_coherent(float2 *p, float2 v) {
+  uint64_t b;
+  __builtin_memcpy(&b, &v, 8);
+  __hip_atomic_store(reinterpret_cast<uint64_t *>(p), b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ float2 load_coherent(const float2 *p) {
+  const uint64_t b = __hip_atomic_load(reinterpret_cast<const uint64_t *>(p), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+  float2 v;
+  __builtin_memcpy(&v, &b, 8);
+  return v;
+}
+
+enum { LD_PLAIN = 0, LD_STREAM = 1, LD_COHERENT = 2 };
+
 struct AccArgs {
   const Chan *chans;
   int n_chan;
@@ -149,6 +179,9 @@ hipError_t launch_pack_kernels(const float2 *kern, const float2 *phase, const in
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t st);
 hipError_t launch_unpack_debug(const void *volt, int fmt, float2 *out, int64_t count, hipStream_t st);
 hipError_t set_lds_limit_ext(const void *fn);
+size_t stream_lds_bytes(int n, int P);
+hipError_t stream_occupancy(int n, int P, int accm, bool jones, int *wgs_per_cu);
+hipError_t launch_stream(int n, int P, int accm, bool jones, const StreamArgs &a, hipStream_t st);
 
 // precision form (256^2 grids, two pols; kernels_mfma.hip)
 constexpr size_t kMfmaTableBytes = (size_t)17 * 2 * 3 * 64 * 8 * 2;

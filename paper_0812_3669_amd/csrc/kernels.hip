@@ -235,8 +235,14 @@ __device__ __forceinline__ void load_volt(const void *row, int fmt, int ant, flo
   }
 }
 
-template <int N, int P, int MODE, bool KJ>
-__global__ __launch_bounds__(kThreads) void k_rows(RowArgs a) {
+// One row band for samples [t_lo, t_hi).  FUSED / GRID: the band grid is built in LDS (cleared, then the
+// deterministic scatter); FFT: it is loaded from the staged grid.  GRID writes the band rows to the staged grid;
+// FUSED and FFT transform the touched rows, and FUSED hands output q of row `row`, pol p, sample t to
+// out(c, t, p, row, q, value) (FFT writes the staged grid).  grid: LDS [P][HB][row_stride(N)]; tws: the
+// transform's twiddle tables, already in LDS and visible to every thread.
+template <int N, int P, int MODE, bool KJ, class Out>
+__device__ __forceinline__ void row_band(const RowArgs &a, int band, int t_lo, int t_hi, float2 *grid,
+                                         const float2 *tws, Out out) {
   static_assert(!KJ || P == 2, "Jones kernels need two pols");
   constexpr int PL = KJ ? 4 : P;                      // packed kernel planes
   using PP = Pipe<N>;
@@ -244,24 +250,12 @@ __global__ __launch_bounds__(kThreads) void k_rows(RowArgs a) {
   static_assert(TS >= N + PP::RMAX - 1, "row stride too small for the padded layout");
   constexpr int HB = band_rows_ce(N, P);             // rows per band
   constexpr int GCH = 8;                             // tap groups whose loads are issued together
-  extern __shared__ float4 smem4[];
-  float2 *grid = reinterpret_cast<float2 *>(smem4);  // [P][HB][TS]
-  float2 *tws = grid + P * HB * TS;                  // [2N] twiddle tables
 
-  int band, tg;
-  if constexpr (MODE == ROW_FUSED) {
-    if (!rows_xcd_map(a, band, tg)) return;
-  } else {
-    band = a.band_begin + (int)(blockIdx.x % a.n_bands);
-    tg = (int)(blockIdx.x / a.n_bands);
-  }
   const Band *bp = a.bands + band;
   struct {
     int chan, row0, r_lo, r_hi;
   } bd = {bp->chan, bp->row0, bp->r_lo, bp->r_hi};
   const int c = bd.chan;
-  const int t_lo = a.t0 + tg * a.t_group;
-  const int t_hi = min(a.t0 + a.nt, t_lo + a.t_group);
   const int nrow = bd.r_hi - bd.r_lo + 1;
   const int ntr = P * nrow;
   const int lane = threadIdx.x & 63;
@@ -270,13 +264,34 @@ __global__ __launch_bounds__(kThreads) void k_rows(RowArgs a) {
   const int gc = bp->grp_cnt[wave];
   const size_t vbytes = (size_t)a.n_ant * P * (a.volt_fmt == 0 ? 2 : 8);   // one (t, c) voltage row
 
-  for (int i = threadIdx.x; i < 2 * N; i += kThreads) tws[i] = a.tw[i];
-
   // transform tr = p * nrow + r (pol p, touched row r); P <= 2, so no division
   auto tr_pol = [&](int tr) { return (P == 2 && tr >= nrow) ? 1 : 0; };
   auto tr_base = [&](int tr) {
     const int p = tr_pol(tr), r = tr - p * nrow;
     return (p * HB + (bd.r_lo - bd.row0 + r)) * TS;
+  };
+
+  // one tap: grid cell m gets w * e (pol by pol; Jones: both pols into each grid)
+  auto scatter_tap = [&](uint32_t m, const float2 (&w)[PL], const float2 (&e)[P]) {
+    const int cell = (int)(m & 0xFFFFu);
+    const int rr = cell / N, col = cell - rr * N;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      float2 *cellp = grid + (p * HB + rr) * TS + col;
+      float2 cur = *cellp;
+      if constexpr (KJ) {
+        // grid p receives both pols: K_{p0} E_0 + K_{p1} E_1
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const float2 wv = w[2 * p + q], ev = e[q];
+          cur = make_float2(cur.x + wv.x * ev.x - wv.y * ev.y, cur.y + wv.x * ev.y + wv.y * ev.x);
+        }
+      } else {
+        const float2 wv = w[p], ev = e[p];
+        cur = make_float2(cur.x + wv.x * ev.x - wv.y * ev.y, cur.y + wv.x * ev.y + wv.y * ev.x);
+      }
+      *cellp = cur;
+    }
   };
 
   for (int t = t_lo; t < t_hi; ++t) {
@@ -290,51 +305,32 @@ __global__ __launch_bounds__(kThreads) void k_rows(RowArgs a) {
       __syncthreads();
       // deterministic scatter: this wavefront's tap groups, one tap per lane, 64 distinct cells per group;
       // the loads of GCH groups are issued before any of them is used
-      const char *vrow = reinterpret_cast<const char *>(a.volt) + ((int64_t)t * a.n_chan + c) * vbytes;
-      for (int g = 0; g < gc; g += GCH) {
-        uint32_t m[GCH];
-        float2 w[GCH][PL];
+      {
+        const char *vrow = reinterpret_cast<const char *>(a.volt) + ((int64_t)t * a.n_chan + c) * vbytes;
+        for (int g = 0; g < gc; g += GCH) {
+          uint32_t m[GCH];
+          float2 w[GCH][PL];
 #pragma unroll
-        for (int k = 0; k < GCH; ++k) {
-          const bool ok = g + k < gc;
-          m[k] = ok ? a.meta[(g0 + g + k) * 64 + lane] : kEmptyTap;
+          for (int k = 0; k < GCH; ++k) {
+            const bool ok = g + k < gc;
+            m[k] = ok ? a.meta[(g0 + g + k) * 64 + lane] : kEmptyTap;
 #pragma unroll
-          for (int p = 0; p < PL; ++p)
-            w[k][p] = ok ? a.wk[((g0 + g + k) * PL + p) * 64 + lane] : make_float2(0.f, 0.f);
-        }
-        float2 e[GCH][P];
-#pragma unroll
-        for (int k = 0; k < GCH; ++k) {
-          if (m[k] != kEmptyTap) {
-            load_volt<P>(vrow, a.volt_fmt, (int)(m[k] >> 16), e[k]);
-          } else {
-#pragma unroll
-            for (int p = 0; p < P; ++p) e[k][p] = make_float2(0.f, 0.f);
+            for (int p = 0; p < PL; ++p)
+              w[k][p] = ok ? a.wk[((g0 + g + k) * PL + p) * 64 + lane] : make_float2(0.f, 0.f);
           }
-        }
+          float2 e[GCH][P];
 #pragma unroll
-        for (int k = 0; k < GCH; ++k) {
-          if (m[k] != kEmptyTap) {
-            const int cell = (int)(m[k] & 0xFFFFu);
-            const int rr = cell / N, col = cell - rr * N;
+          for (int k = 0; k < GCH; ++k) {
+            if (m[k] != kEmptyTap) {
+              load_volt<P>(vrow, a.volt_fmt, (int)(m[k] >> 16), e[k]);
+            } else {
 #pragma unroll
-            for (int p = 0; p < P; ++p) {
-              float2 *cellp = grid + (p * HB + rr) * TS + col;
-              float2 cur = *cellp;
-              if constexpr (KJ) {
-                // grid p receives both pols: K_{p0} E_0 + K_{p1} E_1
-#pragma unroll
-                for (int q = 0; q < 2; ++q) {
-                  const float2 wv = w[k][2 * p + q], ev = e[k][q];
-                  cur = make_float2(cur.x + wv.x * ev.x - wv.y * ev.y, cur.y + wv.x * ev.y + wv.y * ev.x);
-                }
-              } else {
-                const float2 wv = w[k][p], ev = e[k][p];
-                cur = make_float2(cur.x + wv.x * ev.x - wv.y * ev.y, cur.y + wv.x * ev.y + wv.y * ev.x);
-              }
-              *cellp = cur;
+              for (int p = 0; p < P; ++p) e[k][p] = make_float2(0.f, 0.f);
             }
           }
+#pragma unroll
+          for (int k = 0; k < GCH; ++k)
+            if (m[k] != kEmptyTap) scatter_tap(m[k], w[k], e[k]);
         }
       }
       __syncthreads();
@@ -362,14 +358,11 @@ __global__ __launch_bounds__(kThreads) void k_rows(RowArgs a) {
     } else {
       // row FFTs of the touched rows
       constexpr int MB0 = (P * HB * (N / PP::R0) + kThreads - 1) / kThreads;
-      // fused: H in column-group tiles [p][q / W][row][q % W], so that each column-pass workgroup reads one
-      // contiguous tile; staged: natural row-major grid
+      // staged: natural row-major grid
       auto dst = [&](int tr, int q, float2 v) {
         const int p = tr_pol(tr), row = bd.r_lo + tr - p * nrow;
         if constexpr (MODE == ROW_FUSED) {
-          constexpr int W = cols_ce(N);
-          store_stream(a.io + (((int64_t)(c - a.c0) * a.t_block + (t - a.t0)) * P + p) * N * N +
-                           (int64_t)(q / W) * (N * W) + row * W + (q % W), v);
+          out(c, t, p, row, q, v);
         } else {
           a.io[(int64_t)t * a.sample_stride + (int64_t)P * a.chans[c].pix_off + (int64_t)p * N * N +
                (int64_t)row * N + q] = v;
@@ -391,6 +384,35 @@ __global__ __launch_bounds__(kThreads) void k_rows(RowArgs a) {
   }
 }
 
+// Fused / staged row pass: one workgroup per (row band, group of t_group samples).  Fused output goes to the
+// launch block's H in column-group tiles [p][q / W][row][q % W], so that each column-pass workgroup reads one
+// contiguous tile.
+template <int N, int P, int MODE, bool KJ>
+__global__ __launch_bounds__(kThreads) void k_rows(RowArgs a) {
+  constexpr int TS = row_stride(N);
+  constexpr int HB = band_rows_ce(N, P);
+  extern __shared__ float4 smem4[];
+  float2 *grid = reinterpret_cast<float2 *>(smem4);  // [P][HB][TS]
+  float2 *tws = grid + P * HB * TS;                  // [2N] twiddle tables
+
+  int band, tg;
+  if constexpr (MODE == ROW_FUSED) {
+    if (!rows_xcd_map(a, band, tg)) return;
+  } else {
+    band = a.band_begin + (int)(blockIdx.x % a.n_bands);
+    tg = (int)(blockIdx.x / a.n_bands);
+  }
+  for (int i = threadIdx.x; i < 2 * N; i += kThreads) tws[i] = a.tw[i];
+  const int t_lo = a.t0 + tg * a.t_group;
+  const int t_hi = min(a.t0 + a.nt, t_lo + a.t_group);
+  row_band<N, P, MODE, KJ>(a, band, t_lo, t_hi, grid, tws, [&](int c, int t, int p, int row, int q, float2 v) {
+    constexpr int W = cols_ce(N);
+    store_stream(a.io + (((int64_t)(c - a.c0) * a.t_block + (t - a.t0)) * P + p) * N * N +
+                     (int64_t)(q / W) * (N * W) + row * W + (q % W),
+                 v);
+  });
+}
+
 // ------------------------------------------------------------------------------------------------------------
 // Column pass
 // ------------------------------------------------------------------------------------------------------------
@@ -401,8 +423,15 @@ __device__ __forceinline__ float swap_pair(float v) {
   return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
 }
 
-template <int N, int P, int W, int MODE, int ACC>
-__global__ __launch_bounds__(kThreads) void k_cols(ColArgs a) {
+// One column group (W columns of channel c) for samples [t_begin, t_end): column FFTs (first stage straight
+// from global memory, only rows some footprint touched), then (FUSED) XX, YY, XY products summed in registers
+// and added once to the accumulator, or (FFT) the transformed columns written back to the staged grid.
+// src(t): the sample's row-transformed data (FUSED: column-group tiles [p][q / W][row][q % W]; FFT: the staged
+// grid).  pre(t) runs (uniformly) before the loads of sample t are issued, post(t) once every thread has
+// consumed them.  LD: plain, non-temporal or device-coherent loads.  buf: LDS [P][W][Pipe<N>::TS]; tws: twiddle tables in LDS.
+template <int N, int P, int W, int MODE, int ACC, int LD, bool PREFETCH, class Src, class Pre, class Post>
+__device__ __forceinline__ void col_group(const ColArgs &a, int c, int cg, int t_begin, int t_end, float2 *buf,
+                                          const float2 *tws, Src src, Pre pre, Post post) {
   using PP = Pipe<N>;
   constexpr int TS = PP::TS;
   constexpr int R0 = PP::R0, NB0 = N / R0;
@@ -412,22 +441,10 @@ __global__ __launch_bounds__(kThreads) void k_cols(ColArgs a) {
   constexpr int NSL = P * W * NBL;                    // last-stage butterflies (one pol each)
   constexpr int MBL = (NSL + kThreads - 1) / kThreads;
   constexpr int PA = P == 2 ? 2 : 1;                  // accumulator reals per pixel and lane
-  extern __shared__ float4 smem4[];
-  float2 *buf = reinterpret_cast<float2 *>(smem4);   // [P][W][TS]
-  float2 *tws = buf + P * W * TS;                     // [2N] twiddle tables
 
-  int c, cg;
-  if constexpr (MODE == COL_FUSED) {
-    if (!cols_xcd_map(a, N / W, c, cg)) return;
-  } else {
-    c = a.c0 + (int)(blockIdx.x / (N / W));
-    cg = (int)(blockIdx.x % (N / W));
-  }
   const int col0 = cg * W;
   const int jmin = a.chans[c].jmin, jmax = a.chans[c].jmax;
   const int64_t pstride = (int64_t)N * N;
-
-  for (int i = threadIdx.x; i < 2 * N; i += kThreads) tws[i] = a.tw[i];
 
   float acc[MBL][RL][PA];
 #pragma unroll
@@ -437,20 +454,10 @@ __global__ __launch_bounds__(kThreads) void k_cols(ColArgs a) {
 #pragma unroll
       for (int k = 0; k < PA; ++k) acc[s][r][k] = 0.f;
 
-  const int per = (a.nt + (int)gridDim.y - 1) / (int)gridDim.y;
-  const int t_begin = a.t0 + (int)blockIdx.y * per;
-  const int t_end = min(a.t0 + a.nt, t_begin + per);
-
-  auto sample_src = [&](int t) -> const float2 * {
-    if constexpr (MODE == COL_FUSED)
-      return a.in + ((int64_t)(c - a.c0) * a.t_block + (t - a.t0)) * P * pstride;
-    else
-      return a.in + (int64_t)t * a.sample_stride + (int64_t)P * a.chans[c].pix_off;
-  };
   // first-stage inputs of one sample, straight from global (rows outside [jmin, jmax] are zero)
   float2 xs[MB0][R0];
   auto load_first = [&](int t) {
-    const float2 *src = sample_src(t);
+    const float2 *sp = src(t);
 #pragma unroll
     for (int s = 0; s < MB0; ++s) {
       const int b = threadIdx.x + s * kThreads;
@@ -459,14 +466,26 @@ __global__ __launch_bounds__(kThreads) void k_cols(ColArgs a) {
       for (int m = 0; m < R0; ++m) {
         const int row = j + m * NB0;
         const int64_t off = MODE == COL_FUSED ? (int64_t)col0 * N + row * W + col : (int64_t)row * N + col0 + col;
-        xs[s][m] = (b < NS1 && row >= jmin && row <= jmax) ? load_stream(src + p * pstride + off)
-                                                           : make_float2(0.f, 0.f);
+        const bool ok = b < NS1 && row >= jmin && row <= jmax;
+        if constexpr (LD == LD_STREAM)
+          xs[s][m] = ok ? load_stream(sp + p * pstride + off) : make_float2(0.f, 0.f);
+        else if constexpr (LD == LD_COHERENT)
+          xs[s][m] = ok ? load_coherent(sp + p * pstride + off) : make_float2(0.f, 0.f);
+        else
+          xs[s][m] = ok ? sp[p * pstride + off] : make_float2(0.f, 0.f);
       }
     }
   };
-  if (t_begin < t_end) load_first(t_begin);
+  if (PREFETCH && t_begin < t_end) {
+    pre(t_begin);
+    load_first(t_begin);
+  }
 
   for (int t = t_begin; t < t_end; ++t) {
+    if constexpr (!PREFETCH) {
+      pre(t);
+      load_first(t);
+    }
     __syncthreads();   // the previous sample's last stage has finished reading buf
 #pragma unroll
     for (int s = 0; s < MB0; ++s) {
@@ -479,8 +498,12 @@ __global__ __launch_bounds__(kThreads) void k_cols(ColArgs a) {
         for (int r = 0; r < R0; ++r) o[pad_addr<N, R0>(j, r)] = xs[s][r];
       }
     }
-    if (t + 1 < t_end) load_first(t + 1);   // in flight during the remaining stages
     __syncthreads();
+    post(t);                // every thread has consumed the inputs of sample t
+    if (PREFETCH && t + 1 < t_end) {   // in flight during the remaining stages
+      pre(t + 1);
+      load_first(t + 1);
+    }
     if constexpr (PP::S == 3) {
       constexpr int R1 = PP::R1, NB1 = N / R1;
       constexpr int NS2 = P * W * NB1;
@@ -592,6 +615,153 @@ __global__ __launch_bounds__(kThreads) void k_cols(ColArgs a) {
         }
       }
     }
+  }
+}
+
+// Fused / staged column pass: one workgroup per (channel, column group), samples split over gridDim.y.
+template <int N, int P, int W, int MODE, int ACC>
+__global__ __launch_bounds__(kThreads) void k_cols(ColArgs a) {
+  extern __shared__ float4 smem4[];
+  float2 *buf = reinterpret_cast<float2 *>(smem4);   // [P][W][TS]
+  float2 *tws = buf + P * W * Pipe<N>::TS;            // [2N] twiddle tables
+
+  int c, cg;
+  if constexpr (MODE == COL_FUSED) {
+    if (!cols_xcd_map(a, N / W, c, cg)) return;
+  } else {
+    c = a.c0 + (int)(blockIdx.x / (N / W));
+    cg = (int)(blockIdx.x % (N / W));
+  }
+  for (int i = threadIdx.x; i < 2 * N; i += kThreads) tws[i] = a.tw[i];
+  const int per = (a.nt + (int)gridDim.y - 1) / (int)gridDim.y;
+  const int t_begin = a.t0 + (int)blockIdx.y * per;
+  const int t_end = min(a.t0 + a.nt, t_begin + per);
+  const int64_t pstride = (int64_t)N * N;
+  auto src = [&](int t) -> const float2 * {
+    if constexpr (MODE == COL_FUSED)
+      return a.in + ((int64_t)(c - a.c0) * a.t_block + (t - a.t0)) * P * pstride;
+    else
+      return a.in + (int64_t)t * a.sample_stride + (int64_t)P * a.chans[c].pix_off;
+  };
+  col_group<N, P, W, MODE, ACC, LD_STREAM, true>(a, c, cg, t_begin, t_end, buf, tws, src, [](int) {}, [](int) {});
+}
+
+// ------------------------------------------------------------------------------------------------------------
+// Streaming form of the fused path: one persistent launch per grid size.
+//
+// Team x (workgroups b with b % 8 == x, which the dispatcher places on XCD x, so a channel's tap tables stay in
+// one L2) processes channels c0 + x + 8 k, their samples in order.  The first G = N / W workgroups of a team own
+// one column group each (column FFTs, products, accumulator update every t_block samples, exactly as k_cols);
+// the others are row workers taking (sample, band) tasks in sample order (exactly k_rows for one sample).
+// Row-transformed samples pass through a ring of S slots per team.  The ring is written and read with
+// device-coherent accesses (they bypass the non-coherent caches and meet at the memory side, where the MALL
+// holds the small ring), so correctness does not depend on where a workgroup runs.  Per slot, two cumulative
+// counters: bands produced and column groups consumed.  A row task for sample u waits until every owner has
+// consumed sample u - S; an owner waits until every band of its sample has been produced.  Producers make their
+// stores complete (vmcnt 0) before the counter increment.  Every wait is bounded: past the spin limit, or once
+// any workgroup has flagged an error, it sets the error flag and returns, so the launch always ends.  The launch
+// needs all its workgroups resident at once: the host sizes it from the occupancy.
+// ------------------------------------------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t ctr_load(const uint32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Whole-workgroup bounded wait until *p >= target (thread 0 polls).
+__device__ __forceinline__ void wg_wait(const uint32_t *p, uint32_t target, int *err, uint32_t limit) {
+  if (threadIdx.x == 0) {
+    uint32_t spins = 0;
+    while (ctr_load(p) < target) {
+      if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+      if (++spins > limit) {
+        __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(8);
+    }
+  }
+  __syncthreads();
+}
+
+// Samples u' in [0, u] with u' mod S == sl.
+__device__ __forceinline__ int64_t slot_count(int64_t u, int sl, int S) { return u < sl ? 0 : (u - sl) / S + 1; }
+
+// Bands produced into slot u % S up to and including sequence index u on XCD x (what the owners of u wait for).
+__device__ __forceinline__ uint32_t stream_prod_target(const StreamArgs &s, int x, int64_t u) {
+  const int S = s.slots, nt = s.r.nt, sl = (int)(u % S);
+  int64_t tot = 0;
+  for (int k = 0; k <= (int)(u / nt); ++k) {
+    const int64_t lo = (int64_t)k * nt, hi = min((int64_t)(k + 1) * nt - 1, u);
+    tot += (int64_t)s.r.chans[s.r.c0 + x + kXcds * k].band_count * (slot_count(hi, sl, S) - slot_count(lo - 1, sl, S));
+  }
+  return (uint32_t)tot;
+}
+
+// Owner of column group w of channel c (k-th channel of XCD x): all samples, accumulator update per t_block.
+template <int N, int P, int W, int ACC>
+__device__ __forceinline__ void stream_owner(const StreamArgs &s, int x, int w, int k, float2 *work, const float2 *tws) {
+  const int S = s.slots, nt = s.r.nt, t0 = s.r.t0;
+  const int64_t slot_elems = (int64_t)P * N * N;
+  const float2 *ring = s.ring + (int64_t)x * S * slot_elems;
+  uint32_t *prod = s.ctr + (int64_t)x * 2 * S, *cons = prod + S;
+  const int c = s.r.c0 + x + kXcds * k;
+  const int64_t ubase = (int64_t)k * nt - t0;   // sequence index of sample t is ubase + t
+  auto src = [&](int t) -> const float2 * { return ring + ((ubase + t) % S) * slot_elems; };
+  auto pre = [&](int t) {
+    const int64_t u = ubase + t;
+    wg_wait(prod + u % S, stream_prod_target(s, x, u), s.err, s.spin_limit);
+  };
+  auto post = [&](int t) {
+    if (threadIdx.x == 0)
+      __hip_atomic_fetch_add(cons + (ubase + t) % S, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  };
+  for (int tb = t0; tb < t0 + nt; tb += s.c.t_block)
+    col_group<N, P, W, COL_FUSED, ACC, LD_COHERENT, false>(s.c, c, w, tb, min(t0 + nt, tb + s.c.t_block), work, tws, src, pre,
+                                              post);
+}
+
+// Row worker r of R on the k-th channel of XCD x: tasks (sample, band) r, r + R, ... in sample order.
+template <int N, int P, int W, bool KJ>
+__device__ __forceinline__ void stream_rows(const StreamArgs &s, int x, int r, int R, int k, float2 *work,
+                                         const float2 *tws) {
+  constexpr int G = N / W;
+  const int S = s.slots, nt = s.r.nt, t0 = s.r.t0;
+  const int64_t slot_elems = (int64_t)P * N * N;
+  float2 *ring = s.ring + (int64_t)x * S * slot_elems;
+  uint32_t *prod = s.ctr + (int64_t)x * 2 * S, *cons = prod + S;
+  const int c = s.r.c0 + x + kXcds * k;
+  const int nb = s.r.chans[c].band_count, bf = s.r.chans[c].band_first;
+  for (int64_t task = r; task < (int64_t)nt * nb; task += R) {
+    const int t = (int)(task / nb), b = (int)(task - (int64_t)t * nb);
+    const int64_t u = (int64_t)k * nt + t;
+    const int sl = (int)(u % S);
+    if (u >= S) wg_wait(cons + sl, (uint32_t)(G * slot_count(u - S, sl, S)), s.err, s.spin_limit);
+    float2 *dst = ring + sl * slot_elems;
+    row_band<N, P, ROW_FUSED, KJ>(s.r, bf + b, t0 + t, t0 + t + 1, work, tws,
+                                  [&](int, int, int p, int row, int q, float2 v) {
+                                    store_coherent(dst + (int64_t)p * N * N + (q / W) * (N * W) + row * W + (q % W), v);
+                                  });
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this thread's slot stores are complete
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(prod + sl, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+template <int N, int P, int W, int ACC, bool KJ>
+__global__ __launch_bounds__(kThreads) void k_stream(StreamArgs s) {
+  constexpr int G = N / W;
+  extern __shared__ float4 smem4[];
+  float2 *tws = reinterpret_cast<float2 *>(smem4);   // [2N] twiddle tables
+  float2 *work = tws + 2 * N;                        // row band grid or column buffer
+  const int x = (int)(blockIdx.x % kXcds), w = (int)(blockIdx.x / kXcds);
+  for (int i = threadIdx.x; i < 2 * N; i += kThreads) tws[i] = s.r.tw[i];
+  __syncthreads();
+  const int nch = x < s.n_chan_group ? (s.n_chan_group - x + kXcds - 1) / kXcds : 0;
+  const int R = s.wgs_per_xcd - G;
+  for (int k = 0; k < nch; ++k) {
+    if (w < G)
+      stream_owner<N, P, W, ACC>(s, x, w, k, work, tws);
+    else if (R > 0)
+      stream_rows<N, P, W, KJ>(s, x, w - G, R, k, work, tws);
   }
 }
 
@@ -851,6 +1021,51 @@ hipError_t launch_unpack_debug(const void *volt, int fmt, float2 *out, int64_t c
   if (count == 0) return hipSuccess;
   hipLaunchKernelGGL(k_unpack_debug, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, volt, fmt, out,
                      count);
+  return hipGetLastError();
+}
+
+
+template <int N, int P, int W>
+static void *stream_fn(int accm, bool jones) {
+  if constexpr (P == 2) {
+    if (jones) return accm == 0 ? (void *)k_stream<N, P, W, 0, true> : (void *)k_stream<N, P, W, 1, true>;
+  }
+  return accm == 0 ? (void *)k_stream<N, P, W, 0, false> : (void *)k_stream<N, P, W, 1, false>;
+}
+
+static void *stream_kernel(int n, int P, int accm, bool jones) {
+#define SCASE(NN)                                                                                        \
+  case NN:                                                                                               \
+    return P == 2 ? stream_fn<NN, 2, cols_ce(NN)>(accm, jones) : stream_fn<NN, 1, cols_ce(NN)>(accm, jones);
+  switch (n) {
+    SCASE(32) SCASE(64) SCASE(96) SCASE(128) SCASE(160) SCASE(192) SCASE(256) SCASE(320) SCASE(384) SCASE(512)
+    default: return nullptr;
+  }
+#undef SCASE
+}
+
+size_t stream_lds_bytes(int n, int P) {
+  const size_t rows = (size_t)P * band_rows_ce(n, P) * row_stride(n) * 8;
+  const size_t cols = cols_lds_bytes(n, P, cols_ce(n)) - (size_t)2 * n * 8;
+  return (size_t)2 * n * 8 + (rows > cols ? rows : cols);
+}
+
+hipError_t stream_occupancy(int n, int P, int accm, bool jones, int *wgs_per_cu) {
+  void *fn = stream_kernel(n, P, accm, jones);
+  if (!fn) return hipErrorInvalidValue;
+  hipError_t e = set_lds_limit_ext(fn);
+  if (e != hipSuccess) return e;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(wgs_per_cu, (const void *)fn, kThreads,
+                                                      stream_lds_bytes(n, P));
+}
+
+hipError_t launch_stream(int n, int P, int accm, bool jones, const StreamArgs &a, hipStream_t st) {
+  void *fn = stream_kernel(n, P, accm, jones);
+  if (!fn) return hipErrorInvalidValue;
+  hipError_t e = set_lds_limit_ext(fn);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((void (*)(StreamArgs))fn, dim3(kXcds * a.wgs_per_xcd), dim3(kThreads), stream_lds_bytes(n, P),
+                     st, a);
   return hipGetLastError();
 }
 

@@ -110,7 +110,65 @@ int band_count(const moff::Plan &p, const moff::Block &b) {
   return p.chans[b.c1 - 1].band_first + p.chans[b.c1 - 1].band_count - p.chans[b.c0].band_first;
 }
 
-moff_status enqueue_correlate(moff::Plan &p, const void *d_volt, int64_t n_t, void *d_acc, hipStream_t st) {
+moff_status enqueue_two_pass(moff::Plan &p, const void *d_volt, int64_t n_t, void *d_acc, hipStream_t st, int c_lo,
+                             int c_hi);
+
+// Streaming form: per run of channels with one grid size, clear the counters and launch the persistent kernel
+// sized to the device's occupancy (all its workgroups resident at once).
+moff_status enqueue_stream(moff::Plan &p, const void *d_volt, int64_t n_t, void *d_acc, hipStream_t st) {
+  if (n_t > INT32_MAX / 2) return set_err(MOFF_E_INVALID, "n_t too large for one call");
+  const bool jones = is_jones(p);
+  moff::StreamArgs s{};
+  s.r = row_args(p, d_volt);
+  s.r.t0 = 0;
+  s.r.nt = (int)n_t;
+  s.c.chans = d_chans(p);
+  s.c.acc = d_acc;
+  s.c.t_block = p.t_block;
+  s.c.t0 = 0;
+  s.c.nt = (int)n_t;
+  uint32_t *ctr = reinterpret_cast<uint32_t *>(ws(p, p.ws_ctr));
+  s.ring = reinterpret_cast<float2 *>(ws(p, p.ws_ring));
+  s.ctr = ctr;
+  s.err = reinterpret_cast<int *>(ctr + (size_t)moff::kStreamXcds * 2 * moff::kStreamMaxSlots);
+  s.slots = p.stream_slots;
+  s.spin_limit = p.spin_limit;
+  HIP_TRY(moff::launch_fill_zero(ctr, moff::kStreamCtrBytes, st), "clear stream counters");
+  for (int c0 = 0; c0 < p.n_chan;) {
+    const int n = p.chans[c0].n;
+    int c1 = c0;
+    while (c1 < p.n_chan && p.chans[c1].n == n) ++c1;
+    int occ = 0;
+    HIP_TRY(moff::stream_occupancy(n, p.n_pol, p.acc_mode, jones, &occ), "stream occupancy");
+    const int per_xcd = occ * (p.cu_count / moff::kStreamXcds);
+    const int owners = n / p.chans[c0].cols;
+    if (per_xcd < owners + owners / 2) {
+      // too few resident workgroups for column owners plus row workers: this grid size runs two-pass
+      moff_status r = enqueue_two_pass(p, d_volt, n_t, d_acc, st, c0, c1);
+      if (r) return r;
+      c0 = c1;
+      continue;
+    }
+    if (c0 > 0)
+      HIP_TRY(moff::launch_fill_zero(ctr, (size_t)moff::kStreamXcds * 2 * moff::kStreamMaxSlots * 4, st),
+              "clear stream counters");
+    s.r.c0 = s.c.c0 = c0;
+    s.r.tw = s.c.tw = d_tw(p, n);
+    s.n_chan_group = c1 - c0;
+    s.wgs_per_xcd = per_xcd;
+    {
+      ProfScope ps(p, st, 2, n_t * (c1 - c0));
+      HIP_TRY(moff::launch_stream(n, p.n_pol, p.acc_mode, jones, s, st), "streaming pass");
+      HIP_TRY(ps.done(), "profile event");
+    }
+    c0 = c1;
+  }
+  return MOFF_OK;
+}
+
+// Two-pass form for the channels [c_lo, c_hi) (a union of launch blocks).
+moff_status enqueue_two_pass(moff::Plan &p, const void *d_volt, int64_t n_t, void *d_acc, hipStream_t st, int c_lo,
+                             int c_hi) {
   float2 *H = reinterpret_cast<float2 *>(ws(p, p.ws_h));
   const bool jones = is_jones(p);
   moff::RowArgs a = row_args(p, d_volt);
@@ -123,6 +181,7 @@ moff_status enqueue_correlate(moff::Plan &p, const void *d_volt, int64_t n_t, vo
   for (int64_t t0 = 0; t0 < n_t; t0 += p.t_block) {
     const int nt = (int)std::min<int64_t>(p.t_block, n_t - t0);
     for (const moff::Block &b : p.blocks) {
+      if (b.c0 < c_lo || b.c1 > c_hi) continue;
       a.band_begin = band_begin(p, b);
       a.n_bands = band_count(p, b);
       a.c0 = b.c0;
@@ -165,6 +224,11 @@ moff_status enqueue_correlate(moff::Plan &p, const void *d_volt, int64_t n_t, vo
     }
   }
   return MOFF_OK;
+}
+
+moff_status enqueue_correlate(moff::Plan &p, const void *d_volt, int64_t n_t, void *d_acc, hipStream_t st) {
+  if (p.pipeline == MOFF_PIPELINE_STREAM && p.fft_mode == MOFF_FFT_FP32) return enqueue_stream(p, d_volt, n_t, d_acc, st);
+  return enqueue_two_pass(p, d_volt, n_t, d_acc, st, 0, p.n_chan);
 }
 
 void drop_graphs(moff::Plan &p) {
@@ -286,6 +350,9 @@ moff_status moff_bind(moff_plan_t plan, void *d_ws, size_t bytes, void *stream) 
     HIP_TRY(moff::launch_mfma_table(reinterpret_cast<uint16_t *>(ws(p, p.ws_mfma)),
                                     p.fft_mode == MOFF_FFT_SPLIT_BF16, st),
             "split-transform matrices");
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev), "device");
+  HIP_TRY(hipDeviceGetAttribute(&p.cu_count, hipDeviceAttributeMultiprocessorCount, dev), "compute units");
   p.bound = true;
   return ok();
 }
@@ -479,6 +546,30 @@ moff_status moff_set_launch_shape(moff_plan_t plan, int32_t time_block, int32_t 
     return set_err(MOFF_E_BUDGET, "bound workspace too small for this launch shape");
   }
   drop_graphs(p);
+  return ok();
+}
+
+moff_status moff_set_pipeline(moff_plan_t plan, int32_t pipeline) {
+  if (!plan) return set_err(MOFF_E_INVALID, "null plan");
+  moff::Plan &p = plan->p;
+  if (pipeline != MOFF_PIPELINE_TWO_PASS && pipeline != MOFF_PIPELINE_STREAM)
+    return set_err(MOFF_E_INVALID, "unknown pipeline");
+  if (pipeline == MOFF_PIPELINE_STREAM && p.fft_mode != MOFF_FFT_FP32)
+    return set_err(MOFF_E_UNSUPPORTED, "the streaming form is built for the FP32 transform");
+  drop_graphs(p);
+  p.pipeline = pipeline;
+  return ok();
+}
+
+moff_status moff_stream_status(moff_plan_t plan, int32_t *code) {
+  if (!plan || !code) return set_err(MOFF_E_INVALID, "null argument");
+  moff::Plan &p = plan->p;
+  moff_status s = need_bound(p, false);
+  if (s) return s;
+  HIP_TRY(hipDeviceSynchronize(), "synchronize");
+  const uint32_t *ctr = reinterpret_cast<const uint32_t *>(ws(p, p.ws_ctr));
+  HIP_TRY(hipMemcpy(code, ctr + (size_t)moff::kStreamXcds * 2 * moff::kStreamMaxSlots, 4, hipMemcpyDeviceToHost),
+          "read stream status");
   return ok();
 }
 

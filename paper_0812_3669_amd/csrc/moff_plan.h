@@ -10,6 +10,11 @@
 
 namespace moff {
 
+constexpr int kStreamXcds = 8;          // XCDs of the device (workgroup b runs on XCD b % 8)
+constexpr int kStreamMaxSlots = 8;
+// counters [kStreamXcds][2][kStreamMaxSlots] uint32, then the error flag (16 bytes)
+constexpr size_t kStreamCtrBytes = (size_t)kStreamXcds * 2 * kStreamMaxSlots * 4 + 16;
+
 constexpr int kThreads = 256;         // threads per workgroup of every hot-path kernel
 constexpr int kWaves = kThreads / 64;  // wavefronts per workgroup (64-wide on CDNA)
 constexpr int kGroupLanes = 64;       // taps per scatter group (one wavefront instruction)
@@ -66,6 +71,10 @@ struct Plan {
   int32_t chans_per_block = 16;
   int32_t t_block = 16;                 // samples per fused launch block
   int32_t t_group = 4;                  // samples per row-pass workgroup
+  int32_t pipeline = 0;                 // moff_pipeline of the fused path
+  int32_t stream_slots = 3;             // ring slots per XCD (streaming form)
+  uint32_t spin_limit = 1u << 22;       // bounded waits of the streaming form
+  int32_t cu_count = 0;                 // compute units of the bound device
   int64_t pix_total = 0;                // sum of n_c^2
 
   // workspace layout (byte offsets)
@@ -76,6 +85,7 @@ struct Plan {
   size_t ws_chans = 0;                  // Chan array (device copy)
   size_t ws_meta = 0, ws_kidx = 0, ws_gchan = 0, ws_wk = 0;  // tap groups; packed kernels float2 [G][P][64]
   size_t ws_mfma = 0;                   // split-transform matrices (split fft modes only)
+  size_t ws_ring = 0, ws_ctr = 0;       // streaming form: per-XCD ring of row-transformed samples; counters
   size_t ws_h = 0, ws_h_bytes = 0;      // row-pass output of one launch block
   size_t ws_total = 0;
 

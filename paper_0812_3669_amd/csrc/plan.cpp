@@ -274,6 +274,17 @@ moff_status build_plan(const moff_plan_desc &d, Plan &p, std::string *err) {
   off = align256(off + (size_t)p.n_groups * p.kplanes() * kGroupLanes * 8);
   p.ws_mfma = off;
   if (p.fft_mode != MOFF_FFT_FP32) off = align256(off + kMfmaTableBytesHost);
+  // streaming form: kStreamXcds rings of stream_slots row-transformed samples of the largest grid, then the
+  // counters [kStreamXcds][2][slots] and the error flag
+  p.stream_slots = env_int("MOFF_STREAM_SLOTS", 3, 2, kStreamMaxSlots);
+  p.spin_limit = (uint32_t)env_int("MOFF_SPIN_LIMIT", 1 << 22, 1 << 10, 1 << 28);
+  p.pipeline = env_int("MOFF_PIPELINE", 0, 0, 1);
+  int nmax = 0;
+  for (int c = 0; c < C; ++c) nmax = std::max(nmax, p.chans[c].n);
+  p.ws_ring = off;
+  off = align256(off + (size_t)kStreamXcds * p.stream_slots * P * nmax * nmax * 8);
+  p.ws_ctr = off;
+  off = align256(off + kStreamCtrBytes);
   p.ws_h = off;
   layout_blocks(p, tb, cpb, tg);
   return MOFF_OK;

@@ -148,3 +148,17 @@ def test_jones_kernels_pack_four_planes():
     # the packed kernel table doubles (four planes instead of two); nothing else in the workspace changes
     assert jones.workspace_bytes > diag.workspace_bytes
     assert jones.acc_bytes == diag.acc_bytes
+
+
+def test_pipeline_validation():
+    xy = np.array([[1.0, 2.0], [-3.0, 4.0]])
+    plan = Plan(xy, [configs.C_LIGHT], [256], n_pol=2, ksize=4, fft_mode=1)
+    with pytest.raises(MoffError) as ei:
+        plan.set_pipeline(1)
+    assert ei.value.status == 4
+    plan = Plan(xy, [configs.C_LIGHT], [32], n_pol=2, ksize=4)
+    with pytest.raises(MoffError) as ei:
+        plan.set_pipeline(5)
+    assert ei.value.status == 1
+    plan.set_pipeline(1)
+    plan.set_pipeline(0)
