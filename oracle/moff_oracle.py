@@ -233,6 +233,60 @@ def image_pixels(volts: np.ndarray, kern: np.ndarray, ant_xy_m: np.ndarray, freq
     return acc
 
 
+# ---------------------------------------------------------------------------------------------------------
+# Electric-field image tap and feedback calibration (Section 6; Eqs. FBeq1-FBeq3 and the gain update)
+# ---------------------------------------------------------------------------------------------------------
+def antenna_beams(kern: np.ndarray, origin: np.ndarray, n: int, pix: np.ndarray) -> np.ndarray:
+    """B_a(q, p) = sum_{y, x} K_a[y, x] D[j0 + y, q] D[i0 + x, p]: the E-field image of a unit voltage on
+    antenna a alone, at centred pixels pix int [M, 2] (q, p).  kern [A, K, K] -> complex128 [M, A].
+    By linearity the image pixel is E~(q, p) = sum_a B_a(q, p) E_a: each antenna's calibrated gain toward
+    that direction, the g_i of the feedback-calibration equations."""
+    A, K = kern.shape[0], kern.shape[1]
+    D = dft_matrix(n)
+    rows = origin[:, 0][:, None] + np.arange(K)[None, :]          # [A, K] grid rows j0 + y
+    cols = origin[:, 1][:, None] + np.arange(K)[None, :]          # [A, K] grid columns i0 + x
+    out = np.empty((pix.shape[0], A), dtype=np.complex128)
+    k128 = kern.astype(np.complex128)
+    for m, (q, p) in enumerate(pix):
+        dr = D[rows, q]                                            # [A, K]
+        dc = D[cols, p]                                            # [A, K]
+        out[m] = np.einsum("ayx,ay,ax->a", k128, dr, dc)
+    return out
+
+
+def feedback_sums(e: np.ndarray, e_tap: np.ndarray):
+    """The correlations of the feedback loop over T samples of one channel and pol, as sums over t.
+
+    e complex [T, A] (antenna voltages), e_tap complex [T, M] (E-field image at the calibrator pixels).
+    Returns R [M, A] = sum_t E(theta_m, t) conj(E_a(t)), Pw [M] = sum_t |E(theta_m, t)|^2 (Eq. FBeq1's left
+    side) and V [A] = sum_t |E_a(t)|^2 (the antenna autocorrelations v_aa)."""
+    e = e.astype(np.complex128)
+    e_tap = e_tap.astype(np.complex128)
+    R = e_tap.T @ np.conj(e)
+    Pw = np.sum(np.abs(e_tap) ** 2, axis=0)
+    V = np.sum(np.abs(e) ** 2, axis=0)
+    return R, Pw, V
+
+
+def feedback_solve(R: np.ndarray, Pw: np.ndarray, V: np.ndarray, B: np.ndarray):
+    """Feedback-calibration quantities per calibrator m and antenna i (Section 6), with g_i = B_i(theta_m):
+
+    * S_i = < E(theta) g_i* E_i* >_t = conj(g_i) R_i (Eq. FBeq2's left side; its right side as printed,
+      sum_j g_i g_j* v_ij, is conj(S_i): the reading kept here is the left side).  sum_i S_i = Pw.
+    * X_i = sum over j, k both != i of g_j g_k* v_jk = Pw - S_i - conj(S_i) + |g_i|^2 v_ii: the sum of all
+      visibilities not involving antenna i (Eq. FBeq3 subtracts only S_i; the exact exclusion also removes
+      the column k = i and adds back the doubly removed v_ii term).
+    * u_i = 1 + dg_i / g_i = 2 - N conj(S_i) / Pw: the gain update of the single-calibrator case with the
+      factor N (not 2N, which would give dg_i = -g_i for a perfectly calibrated array; with N it vanishes
+      there), applied as g_i -> u_i g_i, i.e. antenna i's kernel multiplied by u_i.
+    R [M, A], Pw [M], V [A], B [M, A] -> (S, X, u), each complex128 [M, A]."""
+    N = R.shape[1]
+    S = np.conj(B) * R
+    X = Pw[:, None] - S - np.conj(S) + (np.abs(B) ** 2) * V[None, :]
+    u = 2.0 - N * np.conj(S) / Pw[:, None]
+    return S, X, u
+
+
 def relative_errors(gpu: np.ndarray, ora: np.ndarray) -> np.ndarray:
     """Per-product peak-normalised error of one channel's image [n_prod, n, n].
 

@@ -300,3 +300,99 @@ def test_phase_tracking_moves_the_source_to_the_phase_centre():
     assert np.unravel_index(np.argmax(img), img.shape) == (n // 2, n // 2)
     A = cells.shape[0]
     assert abs(img[n // 2, n // 2] - A * A * np.sum(np.abs(s) ** 2)) < 1e-9 * A * A * np.sum(np.abs(s) ** 2)
+
+
+# ---------------------------------------------------------------------------------------------------------
+# Electric-field tap and feedback calibration (Section 6)
+# ---------------------------------------------------------------------------------------------------------
+def _tap_setup(A=30, n=32, T=12, K=4, seed=3, M=3):
+    cfg, geo, kern, volts = _small(1, A=A, n=n, T=T, K=K, seed=seed)
+    origin = _origin(geo.ant_xy_m, geo.freqs_hz[0], cfg.cell_lambda, n, K)
+    e = ora.unpack(volts)[:, 0, :, 0]                                  # [T, A]
+    rng = np.random.default_rng(seed)
+    pix = rng.integers(0, n, size=(M, 2))
+    pix[0] = (n // 2, n // 2)
+    return cfg, geo, kern[0, :, 0], origin, e, pix, n
+
+
+def test_antenna_beam_closed_form_for_a_delta_kernel():
+    """One antenna, a single unit tap at (y0, x0): its beam is exp(+2 pi i (row (q - n/2) + col (p - n/2)) / n)
+    at the tap's grid cell (row, col) = origin + (y0, x0), written here with numpy's exp."""
+    n, K = 32, 4
+    kern = np.zeros((1, K, K), dtype=np.complex64)
+    kern[0, 1, 2] = 1.0
+    origin = np.array([[9, 17]])
+    pix = np.array([[3, 30], [16, 16], [21, 5]])
+    B = ora.antenna_beams(kern, origin, n, pix)[:, 0]
+    row, col = 9 + 1, 17 + 2
+    ref = np.exp(2j * np.pi * (row * (pix[:, 0] - n // 2) + col * (pix[:, 1] - n // 2)) / n)
+    assert np.abs(B - ref).max() < 1e-12
+
+
+def test_tap_is_the_sum_of_antenna_beams():
+    """E~ at a pixel from the grid-and-transform route equals sum_a B_a E_a (linearity of W^T and F^T)."""
+    cfg, geo, kern, origin, e, pix, n = _tap_setup()
+    tap = ora.efield_pixels(ora.grid_many(e, kern, origin, n), pix)   # [T, M]
+    B = ora.antenna_beams(kern, origin, n, pix)                        # [M, A]
+    assert _peak_err(e @ B.T, tap) < 1e-12
+
+
+def test_feedback_sums_partition_the_calibrator_power():
+    """sum_i S_i = <|E(theta)|^2>: the per-antenna correlations of Eq. FBeq2 add up to Eq. FBeq1, and
+    <|E(theta)|^2> is the image pixel itself."""
+    cfg, geo, kern, origin, e, pix, n = _tap_setup()
+    tap = ora.efield_pixels(ora.grid_many(e, kern, origin, n), pix)
+    R, Pw, V = ora.feedback_sums(e, tap)
+    B = ora.antenna_beams(kern, origin, n, pix)
+    S, X, u = ora.feedback_solve(R, Pw, V, B)
+    assert np.abs(S.sum(axis=1) - Pw).max() < 1e-12 * Pw.max()
+    img = ora.image(ora.unpack(_small(1, A=30, n=32, T=12, K=4, seed=3)[3]), kern[None, :, None],
+                    geo.ant_xy_m, geo.freqs_hz, [n], cfg.cell_lambda)[0][0]
+    assert np.abs(img[pix[:, 0], pix[:, 1]].real - Pw).max() < 1e-9 * Pw.max()
+
+
+def test_exclusion_sum_against_brute_force_visibilities():
+    """X_i = sum over j, k != i of g_j g_k* v_jk, from the visibility matrix v_jk = sum_t E_j conj(E_k)."""
+    cfg, geo, kern, origin, e, pix, n = _tap_setup(A=12, T=9)
+    tap = ora.efield_pixels(ora.grid_many(e, kern, origin, n), pix)
+    R, Pw, V = ora.feedback_sums(e, tap)
+    B = ora.antenna_beams(kern, origin, n, pix)
+    S, X, u = ora.feedback_solve(R, Pw, V, B)
+    vis = e.T @ np.conj(e)                                             # v_jk
+    A = e.shape[1]
+    for m in range(pix.shape[0]):
+        g = B[m]
+        for i in range(A):
+            keep = np.arange(A) != i
+            ref = np.sum(g[keep][:, None] * np.conj(g[keep])[None, :] * vis[np.ix_(keep, keep)])
+            assert abs(X[m, i] - ref) < 1e-10 * abs(Pw[m])
+    # the printed Eq. FBeq3 (total minus S_i only) differs from the exact exclusion
+    assert np.abs((Pw[:, None] - S) - X).max() > 1e-3 * Pw.max()
+
+
+def test_gain_update_is_stationary_when_calibrated_and_corrects_errors():
+    """One calibrator, no noise: antenna i's voltage is a_i s(t).  With every g_i a_i = 1 the update factor
+    is exactly 1 (with the printed factor 2N it would be -1); with a few antennas off by (1 + d_i), one update
+    g_i -> u_i g_i leaves them off by O(d^2 + d / N)."""
+    rng = np.random.default_rng(11)
+    A, T, n, K = 64, 16, 32, 4
+    kern = (rng.standard_normal((A, K, K)) + 1j * rng.standard_normal((A, K, K))).astype(np.complex64)
+    origin = rng.integers(2, n - K - 2, size=(A, 2))
+    pix = np.array([[n // 2 + 3, n // 2 - 5]])
+    B = ora.antenna_beams(kern, origin, n, pix)[0]                     # g_i toward the calibrator
+    s = rng.standard_normal(T) + 1j * rng.standard_normal(T)
+    for d_scale in (0.0, 0.05):
+        d = np.zeros(A, dtype=np.complex128)
+        bad = rng.choice(A, 8, replace=False)
+        d[bad] = d_scale * (rng.standard_normal(8) + 1j * rng.standard_normal(8)) / np.sqrt(2)
+        a = (1 + d) / B                                                # true responses: g_i a_i = 1 + d_i
+        e = s[:, None] * a[None, :]
+        tap = ora.efield_pixels(ora.grid_many(e, kern, origin, n), pix)
+        R, Pw, V = ora.feedback_sums(e, tap)
+        S, X, u = ora.feedback_solve(R, Pw, V, B[None, :])
+        if d_scale == 0.0:
+            assert np.abs(u - 1).max() < 1e-9
+        else:
+            before = np.abs(B * a - 1).max()
+            after = np.abs(u[0] * B * a - 1).max()
+            assert before > 0.02 and after < 0.2 * before, (before, after)
