@@ -87,6 +87,7 @@ typedef struct {
   int32_t chans_per_block;  /* channels per fused launch block (0 = library default, 64) */
   int32_t time_group;       /* samples per row-pass workgroup (0 = library default, 4) */
   int32_t kernel_mode;      /* moff_kernel_mode; Jones needs n_pol = 2 and the FP32 transform */
+  int32_t n_tap;            /* E-field image taps per channel, 0..8 (moff_set_taps) */
 } moff_plan_desc;
 
 /* Host only.  Validates the description, computes every antenna's footprint per channel, bins antennas into
@@ -186,6 +187,34 @@ moff_status moff_correlate_graph(moff_plan_t plan, const void *d_volt, int64_t n
 moff_status moff_set_pipeline(moff_plan_t plan, int32_t pipeline);
 /* Synchronises the device, then reads the streaming form's status code of the last fused call. */
 moff_status moff_stream_status(moff_plan_t plan, int32_t *code);
+
+/* Electric-field image taps and feedback calibration (Section 6; the Discussion notes that each pixel of the
+ * E-field image is a calibrated tied-array beam, fit for pulsar and transient work).
+ *
+ * moff_set_taps: the desc.n_tap pixels of every channel, h_pix int32 [C][n_tap][2] = centred (row, col) as
+ * in moff_read_image's layout (host memory, copied; the tables are uploaded on the stream).
+ * moff_correlate_tap: moff_correlate (two-pass form, whatever the pipeline setting), plus the E-field image
+ * of every sample at the tapped pixels, before squaring: d_tap complex64 [n_t][C][n_tap][P] (fully written).
+ * moff_cal_accumulate adds to d_cal (FP64, caller-zeroed, moff_cal_size bytes) the sums over the n_t samples
+ *   R[c][m][a][p] = sum_t E_tap[t][c][m][p] conj(E[t][c][a][p])   (double2 [C][n_tap][A][P]; Eq. FBeq2's
+ *                   correlation of the image pixel with one antenna's input, before the gain factor)
+ *   Pw[c][m][p]   = sum_t |E_tap[t][c][m][p]|^2                   (double [C][n_tap][P]; Eq. FBeq1)
+ *   V[c][a][p]    = sum_t |E[t][c][a][p]|^2                       (double [C][A][P])
+ * in that order in the buffer.  d_volt and d_tap are those of the same samples.
+ * moff_cal_solve: with g = B_a(theta_m) (the image of a unit voltage on antenna a alone at tap m, i.e. its
+ * kernel's DFT there, computed in FP64 from d_kern, the diagonal kernels [C][A][P][K][K] in use), writes
+ * d_out double2 [3][C][n_tap][A][P]: S = conj(g) R (Eq. FBeq2's left side; the printed right side is its
+ * conjugate), X = Pw - S - conj(S) + |g|^2 V (the exact sum of all visibilities not involving antenna a;
+ * Eq. FBeq3 as printed omits the k = a terms) and u = 2 - A conj(S) / Pw, the single-calibrator gain update
+ * g -> u g (the printed factor 2A would give -g at convergence; A makes it vanish there).  u can be fed back
+ * as the per-antenna factor of moff_set_kernels_phased.  MOFF_E_UNSUPPORTED for Jones kernels. */
+moff_status moff_set_taps(moff_plan_t plan, const int32_t *h_pix, void *stream);
+moff_status moff_correlate_tap(moff_plan_t plan, const void *d_volt, int64_t n_t, void *d_acc, void *d_tap,
+                               void *stream);
+moff_status moff_cal_size(moff_plan_t plan, size_t *bytes);
+moff_status moff_cal_accumulate(moff_plan_t plan, const void *d_volt, const void *d_tap, int64_t n_t, void *d_cal,
+                                void *stream);
+moff_status moff_cal_solve(moff_plan_t plan, const void *d_cal, const void *d_kern, void *d_out, void *stream);
 
 /* Kernel timing (tracing).  moff_profile(plan, 1) starts recording a pair of HIP events around every launch of
  * the fused path on the caller's stream (earlier records are dropped); moff_profile(plan, 0) stops.  After the

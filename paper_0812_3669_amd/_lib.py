@@ -24,6 +24,7 @@ class PlanDesc(C.Structure):
         ("grid_n", C.POINTER(C.c_int32)), ("cell_lambda", C.c_double),
         ("fft_mode", C.c_int32), ("acc_mode", C.c_int32), ("time_block", C.c_int32), ("volt_format", C.c_int32),
         ("chans_per_block", C.c_int32), ("time_group", C.c_int32), ("kernel_mode", C.c_int32),
+        ("n_tap", C.c_int32),
     ]
 
 
@@ -39,6 +40,11 @@ _SIGS = {
     "moff_set_kernels": ([_P, _P, _P], C.c_int),
     "moff_set_kernels_phased": ([_P, _P, _P, _P], C.c_int),
     "moff_set_pipeline": ([_P, C.c_int32], C.c_int),
+    "moff_set_taps": ([_P, C.POINTER(C.c_int32), _P], C.c_int),
+    "moff_correlate_tap": ([_P, _P, C.c_int64, _P, _P, _P], C.c_int),
+    "moff_cal_size": ([_P, C.POINTER(C.c_size_t)], C.c_int),
+    "moff_cal_accumulate": ([_P, _P, _P, C.c_int64, _P, _P], C.c_int),
+    "moff_cal_solve": ([_P, _P, _P, _P, _P], C.c_int),
     "moff_stream_status": ([_P, C.POINTER(C.c_int32)], C.c_int),
     "moff_grid": ([_P, _P, C.c_int64, _P, _P], C.c_int),
     "moff_fft": ([_P, _P, C.c_int64, _P], C.c_int),

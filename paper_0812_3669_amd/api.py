@@ -49,12 +49,12 @@ class Plan:
     def __init__(self, ant_xy_m, freqs_hz, grid_n=None, n_pol: int = 2, ksize: int = 4, cell_lambda: float = 1.0,
                  fft_mode: int = FFT_FP32, acc_mode: int = ACC_FP32, time_block: int = 0,
                  volt_format: int = VOLT_INT8, chans_per_block: int = 0, time_group: int = 0,
-                 kernel_mode: int = KERNEL_DIAG):
+                 kernel_mode: int = KERNEL_DIAG, n_tap: int = 0):
         self.lib = _lib.load()
         xy = np.ascontiguousarray(ant_xy_m, dtype=np.float64)
         fr = np.ascontiguousarray(freqs_hz, dtype=np.float64)
         self.n_ant, self.n_chan, self.n_pol, self.ksize = xy.shape[0], fr.shape[0], n_pol, ksize
-        self.acc_mode, self.volt_format, self.kernel_mode = acc_mode, volt_format, kernel_mode
+        self.acc_mode, self.volt_format, self.kernel_mode, self.n_tap = acc_mode, volt_format, kernel_mode, n_tap
         gn = None
         if grid_n is not None:
             gn = np.ascontiguousarray(np.broadcast_to(np.asarray(grid_n, dtype=np.int32), (self.n_chan,)))
@@ -65,7 +65,7 @@ class Plan:
         d.grid_n = gn.ctypes.data_as(C.POINTER(C.c_int32)) if gn is not None else None
         d.cell_lambda = cell_lambda
         d.fft_mode, d.acc_mode, d.time_block, d.volt_format = fft_mode, acc_mode, time_block, volt_format
-        d.chans_per_block, d.time_group, d.kernel_mode = chans_per_block, time_group, kernel_mode
+        d.chans_per_block, d.time_group, d.kernel_mode, d.n_tap = chans_per_block, time_group, kernel_mode, n_tap
         h = C.c_void_p()
         _check(self.lib.moff_plan(C.byref(d), C.byref(h)), "moff_plan")
         self._h = h
@@ -177,6 +177,63 @@ class Plan:
         self._check_volts(volts, n_t)
         _check(self.lib.moff_correlate_graph(self._h, _ptr(volts), n_t, _ptr(acc), _stream_handle(stream)),
                "moff_correlate_graph")
+
+    # ---- E-field taps and feedback calibration ---------------------------------------------------------------------
+    def set_taps(self, pix, stream=None):
+        """pix int [C, n_tap, 2] (or [n_tap, 2] for every channel): centred (row, col) pixels of each channel."""
+        pix = np.asarray(pix, dtype=np.int32)
+        if pix.ndim == 2:
+            pix = np.broadcast_to(pix, (self.n_chan,) + pix.shape)
+        pix = np.ascontiguousarray(pix)
+        assert pix.shape == (self.n_chan, self.n_tap, 2), pix.shape
+        self._tap_pix = pix
+        _check(self.lib.moff_set_taps(self._h, pix.ctypes.data_as(C.POINTER(C.c_int32)), _stream_handle(stream)),
+               "moff_set_taps")
+        return self
+
+    def new_tap_buffer(self, n_t: int):
+        import torch
+        return torch.empty((n_t, self.n_chan, self.n_tap, self.n_pol), dtype=torch.complex64, device=self.device)
+
+    def correlate_tap(self, volts, acc, tap, n_t: Optional[int] = None, stream=None):
+        """correlate plus the E-field image at the tapped pixels of every sample: tap complex64 [T, C, n_tap, P]."""
+        n_t = volts.shape[0] if n_t is None else n_t
+        self._check_volts(volts, n_t)
+        assert tap.is_contiguous() and tap.numel() >= n_t * self.n_chan * self.n_tap * self.n_pol
+        _check(self.lib.moff_correlate_tap(self._h, _ptr(volts), n_t, _ptr(acc), _ptr(tap), _stream_handle(stream)),
+               "moff_correlate_tap")
+
+    def new_cal(self):
+        import torch
+        b = C.c_size_t()
+        _check(self.lib.moff_cal_size(self._h, C.byref(b)), "moff_cal_size")
+        return torch.zeros(b.value // 8, dtype=torch.float64, device=self.device)
+
+    def cal_accumulate(self, volts, tap, cal, n_t: Optional[int] = None, stream=None):
+        n_t = volts.shape[0] if n_t is None else n_t
+        self._check_volts(volts, n_t)
+        _check(self.lib.moff_cal_accumulate(self._h, _ptr(volts), _ptr(tap), n_t, _ptr(cal), _stream_handle(stream)),
+               "moff_cal_accumulate")
+
+    def split_cal(self, cal):
+        """-> R complex128 [C, n_tap, A, P], Pw float64 [C, n_tap, P], V float64 [C, A, P] (views)."""
+        import torch
+        Cc, M, A, P = self.n_chan, self.n_tap, self.n_ant, self.n_pol
+        nr = Cc * M * A * P
+        R = torch.view_as_complex(cal[:2 * nr].view(nr, 2)).view(Cc, M, A, P)
+        Pw = cal[2 * nr:2 * nr + Cc * M * P].view(Cc, M, P)
+        V = cal[2 * nr + Cc * M * P:2 * nr + Cc * M * P + Cc * A * P].view(Cc, A, P)
+        return R, Pw, V
+
+    def cal_solve(self, cal, kern, stream=None):
+        """-> (S, X, u), each complex128 [C, n_tap, A, P]: the per-antenna correlation with its gain applied,
+        the sum of all visibilities not involving the antenna, and the gain-update factor."""
+        import torch
+        shape = (3, self.n_chan, self.n_tap, self.n_ant, self.n_pol)
+        out = torch.empty(shape, dtype=torch.complex128, device=self.device)
+        _check(self.lib.moff_cal_solve(self._h, _ptr(cal), _ptr(kern), _ptr(out), _stream_handle(stream)),
+               "moff_cal_solve")
+        return out[0], out[1], out[2]
 
     def set_pipeline(self, pipeline: int):
         """PIPELINE_TWO_PASS (row and column kernels) or PIPELINE_STREAM (one persistent launch per grid size)."""

@@ -163,6 +163,42 @@ struct ReadArgs {
   float2 *img;
 };
 
+// Taps and feedback calibration (kernels_cal.hip).
+constexpr int kMaxTaps = 8;
+
+struct TapArgs {
+  const Chan *chans;
+  const float2 *h;           // row-transformed samples of the launch block (fused path)
+  const float2 *tap_tw;      // per (channel, tap): n twiddles exp(+2 pi i j qr / n)
+  const int64_t *tap_tw_off; // [C] offset of the channel's tables in tap_tw
+  const int2 *tap_idx;       // [C][n_tap] (qr, qc) FFT-order indices
+  float2 *out;               // [T][C][n_tap][P]
+  int c0, n_chan_block, t0, nt, t_block, n_chan, n_tap, P;
+};
+
+struct CalArgs {
+  const void *volt;
+  int volt_fmt;
+  const float2 *tap;         // [nt][C][n_tap][P]
+  void *cal;                 // double2 R [C][n_tap][A][P], double Pw [C][n_tap][P], double V [C][A][P]
+  int64_t nt;
+  int n_chan, n_ant, n_tap, P;
+};
+
+struct SolveArgs {
+  const Chan *chans;
+  const void *cal;
+  const float2 *kern;        // [C][A][P][K][K]
+  const int2 *origin;        // [C][A] (j0, i0)
+  const int2 *tap_cpix;      // [C][n_tap] centred (row, col)
+  void *out;                 // double2 [3][C][n_tap][A][P]: S, X, u
+  int n_chan, n_ant, n_tap, P, K;
+};
+
+hipError_t launch_tap(const TapArgs &a, hipStream_t st);
+hipError_t launch_cal_acc(const CalArgs &a, hipStream_t st);
+hipError_t launch_cal_solve(const SolveArgs &a, hipStream_t st);
+
 enum { ROW_MODE_FUSED = 0, ROW_MODE_GRID = 1, ROW_MODE_FFT = 2 };
 enum { COL_MODE_FUSED = 0, COL_MODE_FFT = 1 };
 

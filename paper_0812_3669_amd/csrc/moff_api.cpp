@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <new>
 #include <string>
@@ -111,7 +112,7 @@ int band_count(const moff::Plan &p, const moff::Block &b) {
 }
 
 moff_status enqueue_two_pass(moff::Plan &p, const void *d_volt, int64_t n_t, void *d_acc, hipStream_t st, int c_lo,
-                             int c_hi);
+                             int c_hi, void *d_tap = nullptr);
 
 // Streaming form: per run of channels with one grid size, clear the counters and launch the persistent kernel
 // sized to the device's occupancy (all its workgroups resident at once).
@@ -168,7 +169,7 @@ moff_status enqueue_stream(moff::Plan &p, const void *d_volt, int64_t n_t, void 
 
 // Two-pass form for the channels [c_lo, c_hi) (a union of launch blocks).
 moff_status enqueue_two_pass(moff::Plan &p, const void *d_volt, int64_t n_t, void *d_acc, hipStream_t st, int c_lo,
-                             int c_hi) {
+                             int c_hi, void *d_tap) {
   float2 *H = reinterpret_cast<float2 *>(ws(p, p.ws_h));
   const bool jones = is_jones(p);
   moff::RowArgs a = row_args(p, d_volt);
@@ -203,6 +204,25 @@ moff_status enqueue_two_pass(moff::Plan &p, const void *d_volt, int64_t n_t, voi
         else
           HIP_TRY(moff::launch_rows(b.n, p.n_pol, moff::ROW_MODE_FUSED, jones, a, rgrid, lds, st), "row pass");
         HIP_TRY(ps.done(), "profile event");
+      }
+      if (d_tap) {
+        // E-field image at the tapped pixels, from this block's row-transformed samples
+        moff::TapArgs ta{};
+        ta.chans = d_chans(p);
+        ta.h = H;
+        ta.tap_tw = reinterpret_cast<const float2 *>(ws(p, p.ws_tap_tw));
+        ta.tap_tw_off = reinterpret_cast<const int64_t *>(ws(p, p.ws_tap_twoff));
+        ta.tap_idx = reinterpret_cast<const int2 *>(ws(p, p.ws_tap_idx));
+        ta.out = static_cast<float2 *>(d_tap);
+        ta.c0 = b.c0;
+        ta.n_chan_block = b.c1 - b.c0;
+        ta.t0 = (int)t0;
+        ta.nt = nt;
+        ta.t_block = p.t_block;
+        ta.n_chan = p.n_chan;
+        ta.n_tap = p.n_tap;
+        ta.P = p.n_pol;
+        HIP_TRY(moff::launch_tap(ta, st), "tap");
       }
       const int W = p.chans[b.c0].cols;
       ca.c0 = b.c0;
@@ -350,6 +370,10 @@ moff_status moff_bind(moff_plan_t plan, void *d_ws, size_t bytes, void *stream) 
     HIP_TRY(moff::launch_mfma_table(reinterpret_cast<uint16_t *>(ws(p, p.ws_mfma)),
                                     p.fft_mode == MOFF_FFT_SPLIT_BF16, st),
             "split-transform matrices");
+  if (p.n_tap > 0)
+    HIP_TRY(hipMemcpyAsync(ws(p, p.ws_origin), p.origin.data(), p.origin.size() * 4, hipMemcpyHostToDevice, st),
+            "upload footprint origins");
+  p.taps_set = false;
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev), "device");
   HIP_TRY(hipDeviceGetAttribute(&p.cu_count, hipDeviceAttributeMultiprocessorCount, dev), "compute units");
@@ -546,6 +570,118 @@ moff_status moff_set_launch_shape(moff_plan_t plan, int32_t time_block, int32_t 
     return set_err(MOFF_E_BUDGET, "bound workspace too small for this launch shape");
   }
   drop_graphs(p);
+  return ok();
+}
+
+moff_status moff_set_taps(moff_plan_t plan, const int32_t *h_pix, void *stream) {
+  if (!plan || !h_pix) return set_err(MOFF_E_INVALID, "null argument");
+  moff::Plan &p = plan->p;
+  moff_status s = need_bound(p, false);
+  if (s) return s;
+  if (p.n_tap <= 0) return set_err(MOFF_E_STATE, "the plan was made with n_tap = 0");
+  const int C = p.n_chan, M = p.n_tap;
+  for (int c = 0; c < C; ++c)
+    for (int m = 0; m < M; ++m)
+      for (int k = 0; k < 2; ++k) {
+        const int v = h_pix[((size_t)c * M + m) * 2 + k];
+        if (v < 0 || v >= p.chans[c].n) return set_err(MOFF_E_INVALID, "tap pixel outside the channel's image");
+      }
+  // twiddles exp(+2 pi i j qr / n) of each tap's row index, in FP64 with the angle reduced in integers
+  p.tap_tw_host.clear();
+  p.tap_twoff_host.assign(C, 0);
+  p.tap_idx_host.assign((size_t)C * M * 2, 0);
+  p.tap_cpix_host.assign(h_pix, h_pix + (size_t)C * M * 2);
+  int64_t off = 0;
+  for (int c = 0; c < C; ++c) {
+    const int n = p.chans[c].n;
+    p.tap_twoff_host[c] = off;
+    for (int m = 0; m < M; ++m) {
+      const int row = h_pix[((size_t)c * M + m) * 2], col = h_pix[((size_t)c * M + m) * 2 + 1];
+      const int qr = (row + n / 2) % n, qc = (col + n / 2) % n;   // FFT order of the centred pixel
+      p.tap_idx_host[((size_t)c * M + m) * 2] = qr;
+      p.tap_idx_host[((size_t)c * M + m) * 2 + 1] = qc;
+      for (int j = 0; j < n; ++j) {
+        const long long r = ((long long)j * qr) % n;
+        const double ang = 2.0 * M_PI * (double)r / (double)n;
+        p.tap_tw_host.push_back((float)std::cos(ang));
+        p.tap_tw_host.push_back((float)std::sin(ang));
+      }
+      off += n;
+    }
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  HIP_TRY(hipMemcpyAsync(ws(p, p.ws_tap_tw), p.tap_tw_host.data(), p.tap_tw_host.size() * 4, hipMemcpyHostToDevice,
+                         st), "upload tap twiddles");
+  HIP_TRY(hipMemcpyAsync(ws(p, p.ws_tap_twoff), p.tap_twoff_host.data(), (size_t)C * 8, hipMemcpyHostToDevice, st),
+          "upload tap offsets");
+  HIP_TRY(hipMemcpyAsync(ws(p, p.ws_tap_idx), p.tap_idx_host.data(), p.tap_idx_host.size() * 4,
+                         hipMemcpyHostToDevice, st), "upload tap indices");
+  HIP_TRY(hipMemcpyAsync(ws(p, p.ws_tap_cpix), p.tap_cpix_host.data(), p.tap_cpix_host.size() * 4,
+                         hipMemcpyHostToDevice, st), "upload tap pixels");
+  p.taps_set = true;
+  return ok();
+}
+
+moff_status moff_correlate_tap(moff_plan_t plan, const void *d_volt, int64_t n_t, void *d_acc, void *d_tap,
+                               void *stream) {
+  if (!plan || !d_volt || !d_acc || !d_tap) return set_err(MOFF_E_INVALID, "null argument");
+  moff::Plan &p = plan->p;
+  moff_status s = need_bound(p, true);
+  if (s) return s;
+  if (!p.taps_set) return set_err(MOFF_E_STATE, "taps are not set (moff_set_taps)");
+  if (n_t < 0) return set_err(MOFF_E_INVALID, "n_t must be >= 0");
+  if (n_t > INT32_MAX / 2) return set_err(MOFF_E_INVALID, "n_t too large for one call");
+  return enqueue_two_pass(p, d_volt, n_t, d_acc, static_cast<hipStream_t>(stream), 0, p.n_chan, d_tap);
+}
+
+moff_status moff_cal_size(moff_plan_t plan, size_t *bytes) {
+  if (!plan || !bytes) return set_err(MOFF_E_INVALID, "null argument");
+  const moff::Plan &p = plan->p;
+  const size_t C = p.n_chan, M = p.n_tap, A = p.n_ant, P = p.n_pol;
+  *bytes = C * M * A * P * 16 + C * M * P * 8 + C * A * P * 8;
+  return ok();
+}
+
+moff_status moff_cal_accumulate(moff_plan_t plan, const void *d_volt, const void *d_tap, int64_t n_t, void *d_cal,
+                                void *stream) {
+  if (!plan || !d_volt || !d_tap || !d_cal) return set_err(MOFF_E_INVALID, "null argument");
+  moff::Plan &p = plan->p;
+  if (p.n_tap <= 0) return set_err(MOFF_E_STATE, "the plan was made with n_tap = 0");
+  if (n_t < 0) return set_err(MOFF_E_INVALID, "n_t must be >= 0");
+  moff::CalArgs a{};
+  a.volt = d_volt;
+  a.volt_fmt = p.volt_format;
+  a.tap = static_cast<const float2 *>(d_tap);
+  a.cal = d_cal;
+  a.nt = n_t;
+  a.n_chan = p.n_chan;
+  a.n_ant = p.n_ant;
+  a.n_tap = p.n_tap;
+  a.P = p.n_pol;
+  HIP_TRY(moff::launch_cal_acc(a, static_cast<hipStream_t>(stream)), "calibration sums");
+  return ok();
+}
+
+moff_status moff_cal_solve(moff_plan_t plan, const void *d_cal, const void *d_kern, void *d_out, void *stream) {
+  if (!plan || !d_cal || !d_kern || !d_out) return set_err(MOFF_E_INVALID, "null argument");
+  moff::Plan &p = plan->p;
+  moff_status s = need_bound(p, false);
+  if (s) return s;
+  if (!p.taps_set) return set_err(MOFF_E_STATE, "taps are not set (moff_set_taps)");
+  if (p.kernel_mode != MOFF_KERNEL_DIAG) return set_err(MOFF_E_UNSUPPORTED, "the solve takes diagonal kernels");
+  moff::SolveArgs a{};
+  a.chans = d_chans(p);
+  a.cal = d_cal;
+  a.kern = static_cast<const float2 *>(d_kern);
+  a.origin = reinterpret_cast<const int2 *>(ws(p, p.ws_origin));
+  a.tap_cpix = reinterpret_cast<const int2 *>(ws(p, p.ws_tap_cpix));
+  a.out = d_out;
+  a.n_chan = p.n_chan;
+  a.n_ant = p.n_ant;
+  a.n_tap = p.n_tap;
+  a.P = p.n_pol;
+  a.K = p.ksize;
+  HIP_TRY(moff::launch_cal_solve(a, static_cast<hipStream_t>(stream)), "calibration solve");
   return ok();
 }
 

@@ -52,7 +52,7 @@ struct Plan {
   // description (copied)
   int32_t n_ant = 0, n_pol = 0, n_chan = 0, ksize = 0;
   double cell_lambda = 1.0;
-  int32_t fft_mode = 0, acc_mode = 0, time_block = 0, volt_format = 0, kernel_mode = 0;
+  int32_t fft_mode = 0, acc_mode = 0, time_block = 0, volt_format = 0, kernel_mode = 0, n_tap = 0;
   std::vector<double> ant_xy, freq;
 
   // geometry
@@ -86,13 +86,18 @@ struct Plan {
   size_t ws_meta = 0, ws_kidx = 0, ws_gchan = 0, ws_wk = 0;  // tap groups; packed kernels float2 [G][P][64]
   size_t ws_mfma = 0;                   // split-transform matrices (split fft modes only)
   size_t ws_ring = 0, ws_ctr = 0;       // streaming form: per-XCD ring of row-transformed samples; counters
+  size_t ws_tap_tw = 0, ws_tap_twoff = 0, ws_tap_idx = 0, ws_tap_cpix = 0, ws_origin = 0;   // taps
   size_t ws_h = 0, ws_h_bytes = 0;      // row-pass output of one launch block
   size_t ws_total = 0;
 
   // binding state
   void *d_ws = nullptr;
   size_t ws_bound = 0;
-  bool bound = false, kernels_set = false;
+  bool bound = false, kernels_set = false, taps_set = false;
+  // tap tables staged on the host for the asynchronous upload (kept until the next moff_set_taps)
+  std::vector<float> tap_tw_host;       // float2 per entry
+  std::vector<int64_t> tap_twoff_host;  // [C]
+  std::vector<int32_t> tap_idx_host, tap_cpix_host;   // [C][n_tap][2]
 
   // kernel timing (moff_profile): events are hipEvent_t stored as void*
   struct ProfRec {

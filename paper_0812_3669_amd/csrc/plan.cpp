@@ -75,6 +75,7 @@ moff_status build_plan(const moff_plan_desc &d, Plan &p, std::string *err) {
   if (d.volt_format != MOFF_VOLT_INT8 && d.volt_format != MOFF_VOLT_C64)
     return fail(err, MOFF_E_INVALID, "unknown volt_format");
   if (d.time_block < 0) return fail(err, MOFF_E_INVALID, "time_block must be >= 0");
+  if (d.n_tap < 0 || d.n_tap > 8) return fail(err, MOFF_E_INVALID, "n_tap must be 0..8");
   if (d.kernel_mode != MOFF_KERNEL_DIAG && d.kernel_mode != MOFF_KERNEL_JONES)
     return fail(err, MOFF_E_INVALID, "unknown kernel_mode");
   if (d.kernel_mode == MOFF_KERNEL_JONES && d.n_pol != 2)
@@ -91,6 +92,7 @@ moff_status build_plan(const moff_plan_desc &d, Plan &p, std::string *err) {
   p.acc_mode = d.acc_mode;
   p.volt_format = d.volt_format;
   p.kernel_mode = d.kernel_mode;
+  p.n_tap = d.n_tap;
   p.ant_xy.assign(d.ant_xy_m, d.ant_xy_m + 2 * (size_t)d.n_ant);
   p.freq.assign(d.freq_hz, d.freq_hz + d.n_chan);
   for (double v : p.ant_xy)
@@ -285,6 +287,22 @@ moff_status build_plan(const moff_plan_desc &d, Plan &p, std::string *err) {
   off = align256(off + (size_t)kStreamXcds * p.stream_slots * P * nmax * nmax * 8);
   p.ws_ctr = off;
   off = align256(off + kStreamCtrBytes);
+  // taps: twiddle tables (n per tap per channel), their offsets, FFT-order and centred pixel indices, and the
+  // footprint origins used by the calibration solve
+  if (p.n_tap > 0) {
+    size_t tw = 0;
+    for (int c = 0; c < C; ++c) tw += (size_t)p.n_tap * p.chans[c].n;
+    p.ws_tap_tw = off;
+    off = align256(off + tw * 8);
+    p.ws_tap_twoff = off;
+    off = align256(off + (size_t)C * 8);
+    p.ws_tap_idx = off;
+    off = align256(off + (size_t)C * p.n_tap * 8);
+    p.ws_tap_cpix = off;
+    off = align256(off + (size_t)C * p.n_tap * 8);
+    p.ws_origin = off;
+    off = align256(off + (size_t)C * A * 8);
+  }
   p.ws_h = off;
   layout_blocks(p, tb, cpb, tg);
   return MOFF_OK;

@@ -1,0 +1,112 @@
+"""E-field image taps and the feedback-calibration correlator on the GPU, against the FP64 oracle, and the
+feedback loop (correlator output -> gain update -> kernels) on a noise-free single calibrator.
+
+Tolerance.  A tapped pixel can be arbitrarily weak, so tap values are compared against the sample's E-field
+image RMS, which by Parseval is the grid's Frobenius norm ||G_t||: |gpu - oracle| <= 1e-5 ||G_t||.  The sums
+carry that scale: R[m, a] against sqrt(sum_t ||G_t||^2 V_a), Pw and S, X against sum_t ||G_t||^2 (plus
+|g|^2 V_a for X), and the update factor u = 2 - A conj(S) / Pw at the bright centre pixel against A 1e-5."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import moff_oracle as ora
+from paper_0812_3669_amd import api, configs, synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+TOL = 1e-5
+
+
+def _series_err(gpu, ref):
+    return float(np.abs(gpu - ref).max() / np.abs(ref).max())
+
+
+@pytest.mark.parametrize("P,n,M", [(2, 64, 3), (1, 128, 2)])
+def test_taps_and_calibration_sums(P, n, M):
+    cfg = configs.scaled(configs.PLAIN, index=500 + n, n_ant=40, n_pol=P, n_chan=3, n_time=20, ksize=4, grid_n=n,
+                         disk_lambda=0.6 * n)
+    geo, kern, volts = synth.workload(cfg)
+    plan = api.plan_for(cfg, geo, n_tap=M, time_block=8).bind(DEV)
+    kd = torch.from_numpy(np.ascontiguousarray(kern)).to(DEV)
+    plan.set_kernels(kd)
+    rng = np.random.default_rng(n)
+    pix = rng.integers(0, n, size=(cfg.n_chan, M, 2)).astype(np.int32)
+    pix[:, 0] = (n // 2, n // 2)
+    plan.set_taps(pix)
+    v = torch.from_numpy(volts).to(DEV)
+    acc_t, acc = plan.new_accumulator(), plan.new_accumulator()
+    tap = plan.new_tap_buffer(cfg.n_time)
+    plan.correlate_tap(v, acc_t, tap)
+    plan.correlate(v, acc)
+    cal = plan.new_cal()
+    plan.cal_accumulate(v, tap, cal)
+    S, X, u = (x.cpu().numpy() for x in plan.cal_solve(cal, kd))
+    R, Pw, V = (x.cpu().numpy() for x in plan.split_cal(cal))
+    torch.cuda.synchronize()
+    assert torch.equal(acc_t, acc)                      # the tap does not disturb the image
+    tap = tap.cpu().numpy()
+    e = ora.unpack(volts)
+    for c in range(cfg.n_chan):
+        origin = ora.footprint_origin(geo.ant_xy_m, geo.freqs_hz[c], cfg.cell_lambda, n, cfg.ksize)
+        for p in range(P):
+            ec = e[:, c, :, p]
+            G = ora.grid_many(ec, kern[c, :, p], origin, n)
+            rms = np.sqrt(np.sum(np.abs(G) ** 2, axis=(1, 2)))                # E-field image RMS per sample
+            tref = ora.efield_pixels(G, pix[c])                                # [T, M]
+            for m in range(M):
+                assert np.all(np.abs(tap[:, c, m, p] - tref[:, m]) <= TOL * rms), (c, p, m)
+            Rr, Pr, Vr = ora.feedback_sums(ec, tref)
+            B = ora.antenna_beams(kern[c, :, p], origin, n, pix[c])
+            Sr, Xr, ur = ora.feedback_solve(Rr, Pr, Vr, B)
+            pscale = np.sum(rms ** 2)
+            assert np.all(np.abs(R[c, :, :, p] - Rr) <= TOL * np.sqrt(pscale * Vr)[None, :])
+            assert np.all(np.abs(Pw[c, :, p] - Pr) <= TOL * pscale)
+            assert np.abs(V[c, :, p] - Vr).max() <= 1e-12 * Vr.max()       # integers summed in FP64
+            for m in range(M):
+                gs = np.abs(B[m])
+                assert np.all(np.abs(S[c, m, :, p] - Sr[m]) <= TOL * gs * np.sqrt(pscale * Vr)), (c, p, m)
+                assert np.all(np.abs(X[c, m, :, p] - Xr[m]) <= TOL * (pscale + gs ** 2 * Vr)), (c, p, m)
+                assert abs(S[c, m, :, p].sum() - Pw[c, m, p]) <= TOL * pscale   # sum_i S_i = Pw
+            assert np.abs(u[c, 0, :, p] - ur[0]).max() <= cfg.n_ant * TOL, (c, p)
+
+
+def test_feedback_loop_single_calibrator():
+    """A noise-free calibrator: antenna i's voltage is a_i s(t) with g_i a_i = 1 + d_i (a few d_i != 0).  The
+    correlator's taps feed the calibration sums; the solve's update, applied to the kernels, removes the
+    errors to first order, and a second pass finds the array calibrated (u close to 1)."""
+    n, A, T, K = 32, 64, 24, 4
+    cfg = configs.scaled(configs.TINY, index=600, n_ant=A, n_pol=1, grid_n=n, n_time=T, ksize=K, disk_lambda=20.0,
+                         int8=False)
+    geo = synth.geometry(cfg)
+    rng = np.random.default_rng(5)
+    kern = (rng.standard_normal((1, A, 1, K, K)) + 1j * rng.standard_normal((1, A, 1, K, K))).astype(np.complex64)
+    origin = ora.footprint_origin(geo.ant_xy_m, geo.freqs_hz[0], cfg.cell_lambda, n, K)
+    pix = np.array([[n // 2 + 3, n // 2 - 5]], dtype=np.int32)
+    B = ora.antenna_beams(kern[0, :, 0], origin, n, pix)[0]
+    d = np.zeros(A, dtype=np.complex128)
+    bad = rng.choice(A, 8, replace=False)
+    d[bad] = 0.05 * (rng.standard_normal(8) + 1j * rng.standard_normal(8)) / np.sqrt(2)
+    a = (1 + d) / B
+    s = rng.standard_normal(T) + 1j * rng.standard_normal(T)
+    volts = (s[:, None] * a[None, :]).astype(np.complex64).reshape(T, 1, A, 1)
+    plan = api.plan_for(cfg, geo, n_tap=1).bind(DEV)
+    plan.set_taps(pix)
+    v = torch.from_numpy(volts).to(DEV)
+
+    def one_pass(k):
+        kd = torch.from_numpy(np.ascontiguousarray(k)).to(DEV)
+        plan.set_kernels(kd)
+        acc, tap, cal = plan.new_accumulator(), plan.new_tap_buffer(T), plan.new_cal()
+        plan.correlate_tap(v, acc, tap)
+        plan.cal_accumulate(v, tap, cal)
+        S, X, u = plan.cal_solve(cal, kd)
+        torch.cuda.synchronize()
+        return u.cpu().numpy()[0, 0, :, 0]
+
+    u1 = one_pass(kern)
+    before = np.abs(B * a - 1).max()
+    after = np.abs(u1 * B * a - 1).max()
+    assert before > 0.02 and after < 0.2 * before, (before, after)
+    kern2 = (kern * u1.astype(np.complex64)[None, :, None, None, None]).astype(np.complex64)
+    u2 = one_pass(kern2)
+    assert np.abs(u2 - 1).max() < 0.2 * np.abs(u1 - 1).max()

@@ -162,3 +162,20 @@ def test_pipeline_validation():
     assert ei.value.status == 1
     plan.set_pipeline(1)
     plan.set_pipeline(0)
+
+
+def test_tap_validation_and_sizes():
+    xy = np.array([[1.0, 2.0], [-3.0, 4.0], [5.0, -6.0]])
+    with pytest.raises(MoffError) as ei:
+        Plan(xy, [configs.C_LIGHT], [32], n_pol=2, ksize=4, n_tap=9)
+    assert ei.value.status == 1
+    plain = Plan(xy, [configs.C_LIGHT, 2 * configs.C_LIGHT], [32, 64], n_pol=2, ksize=4)
+    taps = Plan(xy, [configs.C_LIGHT, 2 * configs.C_LIGHT], [32, 64], n_pol=2, ksize=4, n_tap=3)
+    # tap twiddles (n per tap per channel), indices, pixels and footprint origins live in the workspace
+    assert taps.workspace_bytes >= plain.workspace_bytes + 3 * (32 + 64) * 8 + 2 * 3 * 8 * 2 + 2 * 3 * 8
+    b = C.c_size_t()
+    assert taps.lib.moff_cal_size(taps._h, C.byref(b)) == 0
+    assert b.value == 2 * 3 * 3 * 2 * 16 + 2 * 3 * 2 * 8 + 2 * 3 * 2 * 8
+    # taps need a bound plan made with n_tap > 0
+    assert taps.lib.moff_correlate_tap(taps._h, C.c_void_p(1), 1, C.c_void_p(1), C.c_void_p(1), None) == 5
+    assert plain.lib.moff_cal_accumulate(plain._h, C.c_void_p(1), C.c_void_p(1), 1, C.c_void_p(1), None) == 5
