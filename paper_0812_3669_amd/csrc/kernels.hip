@@ -211,35 +211,6 @@ __device__ __forceinline__ void row_stage_out(const float2 *buf, int ntr, const 
   }
 }
 
-// Voltage of antenna `ant` (both pols) for one (t, c) row, read straight from global memory (L1/L2 hits:
-// the row is 2 P bytes per antenna and every band of the channel touches it).
-template <int P>
-__device__ __forceinline__ void load_volt(const void *row, int fmt, int ant, float2 (&e)[P]) {
-  if (fmt == 0) {
-    if constexpr (P == 2) {
-      const uint32_t v = reinterpret_cast<const uint32_t *>(row)[ant];
-      e[0] = make_float2((float)(int8_t)(v & 0xFF), (float)(int8_t)((v >> 8) & 0xFF));
-      e[1] = make_float2((float)(int8_t)((v >> 16) & 0xFF), (float)(int8_t)(v >> 24));
-    } else {
-      const uint16_t v = reinterpret_cast<const uint16_t *>(row)[ant];
-      e[0] = make_float2((float)(int8_t)(v & 0xFF), (float)(int8_t)(v >> 8));
-    }
-  } else {
-    if constexpr (P == 2) {
-      const float4 v = reinterpret_cast<const float4 *>(row)[ant];
-      e[0] = make_float2(v.x, v.y);
-      e[1] = make_float2(v.z, v.w);
-    } else {
-      e[0] = reinterpret_cast<const float2 *>(row)[ant];
-    }
-  }
-}
-
-// One row band for samples [t_lo, t_hi).  FUSED / GRID: the band grid is built in LDS (cleared, then the
-// deterministic scatter); FFT: it is loaded from the staged grid.  GRID writes the band rows to the staged grid;
-// FUSED and FFT transform the touched rows, and FUSED hands output q of row `row`, pol p, sample t to
-// out(c, t, p, row, q, value) (FFT writes the staged grid).  grid: LDS [P][HB][row_stride(N)]; tws: the
-// transform's twiddle tables, already in LDS and visible to every thread.
 template <int N, int P, int MODE, bool KJ, class Out>
 __device__ __forceinline__ void row_band(const RowArgs &a, int band, int t_lo, int t_hi, float2 *grid,
                                          const float2 *tws, Out out) {
@@ -318,16 +289,10 @@ __device__ __forceinline__ void row_band(const RowArgs &a, int band, int t_lo, i
             for (int p = 0; p < PL; ++p)
               w[k][p] = ok ? a.wk[((g0 + g + k) * PL + p) * 64 + lane] : make_float2(0.f, 0.f);
           }
+          // voltages of the GCH groups' taps: branch-free (an empty lane reads antenna 0 and discards it), so
+          // the GCH loads are in flight together
           float2 e[GCH][P];
-#pragma unroll
-          for (int k = 0; k < GCH; ++k) {
-            if (m[k] != kEmptyTap) {
-              load_volt<P>(vrow, a.volt_fmt, (int)(m[k] >> 16), e[k]);
-            } else {
-#pragma unroll
-              for (int p = 0; p < P; ++p) e[k][p] = make_float2(0.f, 0.f);
-            }
-          }
+          load_volts<P, GCH>(vrow, a.volt_fmt, m, e);
 #pragma unroll
           for (int k = 0; k < GCH; ++k)
             if (m[k] != kEmptyTap) scatter_tap(m[k], w[k], e[k]);

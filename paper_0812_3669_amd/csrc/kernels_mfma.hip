@@ -96,23 +96,7 @@ __global__ __launch_bounds__(kThreads) void k_rows_mfma(RowArgs a, const uint16_
           w[k][p] = ok ? a.wk[((g0 + g + k) * MP + p) * 64 + lane] : make_float2(0.f, 0.f);
       }
       float2 e[GCH][MP];
-#pragma unroll
-      for (int k = 0; k < GCH; ++k) {
-        if (m[k] != kEmptyTap) {
-          const int ant = (int)(m[k] >> 16);
-          if (a.volt_fmt == 0) {
-            const uint32_t v = reinterpret_cast<const uint32_t *>(vrow)[ant];
-            e[k][0] = make_float2((float)(int8_t)(v & 0xFF), (float)(int8_t)((v >> 8) & 0xFF));
-            e[k][1] = make_float2((float)(int8_t)((v >> 16) & 0xFF), (float)(int8_t)(v >> 24));
-          } else {
-            const float4 v = reinterpret_cast<const float4 *>(vrow)[ant];
-            e[k][0] = make_float2(v.x, v.y);
-            e[k][1] = make_float2(v.z, v.w);
-          }
-        } else {
-          e[k][0] = e[k][1] = make_float2(0.f, 0.f);
-        }
-      }
+      load_volts<MP, GCH>(vrow, a.volt_fmt, m, e);
 #pragma unroll
       for (int k = 0; k < GCH; ++k) {
         if (m[k] != kEmptyTap) {
@@ -171,16 +155,32 @@ __global__ __launch_bounds__(kThreads) void k_cols_mfma(ColArgs a, const uint16_
 #pragma unroll
     for (int i = 0; i < 4; ++i) acc[jj][i][0] = acc[jj][i][1] = 0.f;
 
+  // the sample's tile (2 pols x 256 rows x 8 columns), 16 values per thread, loaded one sample ahead so the
+  // loads are in flight during the previous sample's transforms
+  constexpr int PER = MP * MN * MW / kThreads;
+  float2 nx[PER];
+  auto load_tile = [&](int t) {
+    const float2 *src = a.in + ((int64_t)(c - a.c0) * a.t_block + (t - a.t0)) * MP * MN * MN + (int64_t)cg * (MN * MW);
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int i = threadIdx.x + k * kThreads;
+      const int pp = i / (MN * MW), rem = i - pp * (MN * MW);
+      const int row = rem / MW;
+      nx[k] = (row >= jmin && row <= jmax) ? load_stream(src + (int64_t)pp * MN * MN + rem) : make_float2(0.f, 0.f);
+    }
+  };
+  if (a.nt > 0) load_tile(a.t0);
   for (int t = a.t0; t < a.t0 + a.nt; ++t) {
     __syncthreads();
-    const float2 *src = a.in + ((int64_t)(c - a.c0) * a.t_block + (t - a.t0)) * MP * MN * MN + (int64_t)cg * (MN * MW);
-    for (int i = threadIdx.x; i < MP * MN * MW; i += kThreads) {
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int i = threadIdx.x + k * kThreads;
       const int pp = i / (MN * MW), rem = i - pp * (MN * MW);
       const int row = rem / MW, cc = rem - row * MW;
-      xs[(pp * MW + cc) * MTS + row] =
-          (row >= jmin && row <= jmax) ? load_stream(src + (int64_t)pp * MN * MN + rem) : make_float2(0.f, 0.f);
+      xs[(pp * MW + cc) * MTS + row] = nx[k];
     }
     __syncthreads();
+    if (t + 1 < a.t0 + a.nt) load_tile(t + 1);
     fft256x16_mfma<BF16>(xs, MTS, ys, mats, [&](int, int, float2 v, int jj, int i) {
       // lanes t and t ^ 8 hold the two pols of one pixel
       const float2 o = make_float2(__shfl_xor(v.x, 8), __shfl_xor(v.y, 8));
