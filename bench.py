@@ -94,7 +94,8 @@ def serving_bench(args, dev):
     free, total = torch.cuda.mem_get_info(dev)
     budget = int(0.8 * free)
     ex = serve.GpuExecutor(dev)
-    sch = serve.Scheduler(ex, hbm_budget=budget, max_slots=8, block=64)
+    sch = serve.Scheduler(ex, hbm_budget=budget, max_slots=8, block=64,
+                          progress=lambda k, n: print(f"bench: {k}/{n} jobs done", file=sys.stderr, flush=True))
     print(f"bench: serving {len(trace)} jobs, HBM budget {budget / 2**30:.1f} GiB", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     st = sch.run(trace, realtime=True)

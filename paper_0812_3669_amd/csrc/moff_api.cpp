@@ -111,6 +111,21 @@ int band_count(const moff::Plan &p, const moff::Block &b) {
   return p.chans[b.c1 - 1].band_first + p.chans[b.c1 - 1].band_count - p.chans[b.c0].band_first;
 }
 
+// Internal stream (default priority) and events of the overlapped two-pass form, created on first use.
+moff_status ensure_overlap(moff::Plan &p) {
+  if (p.row_stream) return MOFF_OK;
+  hipStream_t s;
+  HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "row stream");
+  p.row_stream = s;
+  void **evs[5] = {&p.ev_rows[0], &p.ev_rows[1], &p.ev_cols[0], &p.ev_cols[1], &p.ev_fork};
+  for (void **e : evs) {
+    hipEvent_t ev;
+    HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "overlap event");
+    *e = ev;
+  }
+  return MOFF_OK;
+}
+
 moff_status enqueue_two_pass(moff::Plan &p, const void *d_volt, int64_t n_t, void *d_acc, hipStream_t st, int c_lo,
                              int c_hi, void *d_tap = nullptr);
 
@@ -170,19 +185,35 @@ moff_status enqueue_stream(moff::Plan &p, const void *d_volt, int64_t n_t, void 
 // Two-pass form for the channels [c_lo, c_hi) (a union of launch blocks).
 moff_status enqueue_two_pass(moff::Plan &p, const void *d_volt, int64_t n_t, void *d_acc, hipStream_t st, int c_lo,
                              int c_hi, void *d_tap) {
-  float2 *H = reinterpret_cast<float2 *>(ws(p, p.ws_h));
+  float2 *H0 = reinterpret_cast<float2 *>(ws(p, p.ws_h));
   const bool jones = is_jones(p);
   moff::RowArgs a = row_args(p, d_volt);
-  a.io = H;
   moff::ColArgs ca{};
   ca.chans = d_chans(p);
-  ca.in = H;
   ca.acc = d_acc;
   ca.t_block = p.t_block;
+  // Overlap: the row passes run on an internal stream, block k into buffer k % 2, while the column pass of
+  // block k - 1 runs on the caller's stream; events order rows(k) -> cols(k) and cols(k - 2) -> rows(k).
+  const bool dual = p.overlap != 0;
+  hipStream_t rs = st;
+  if (dual) {
+    moff_status r = ensure_overlap(p);
+    if (r) return r;
+    rs = static_cast<hipStream_t>(p.row_stream);
+    HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(p.ev_fork), st), "fork event");
+    HIP_TRY(hipStreamWaitEvent(rs, static_cast<hipEvent_t>(p.ev_fork), 0), "fork wait");
+  }
+  int64_t k = 0;
   for (int64_t t0 = 0; t0 < n_t; t0 += p.t_block) {
     const int nt = (int)std::min<int64_t>(p.t_block, n_t - t0);
     for (const moff::Block &b : p.blocks) {
       if (b.c0 < c_lo || b.c1 > c_hi) continue;
+      const int slot = dual ? (int)(k % 2) : 0;
+      float2 *H = H0 + (size_t)slot * (p.ws_h_bytes / sizeof(float2));
+      a.io = H;
+      ca.in = H;
+      if (dual && k >= 2)
+        HIP_TRY(hipStreamWaitEvent(rs, static_cast<hipEvent_t>(p.ev_cols[slot]), 0), "buffer reuse wait");
       a.band_begin = band_begin(p, b);
       a.n_bands = band_count(p, b);
       a.c0 = b.c0;
@@ -197,12 +228,12 @@ moff_status enqueue_two_pass(moff::Plan &p, const void *d_volt, int64_t n_t, voi
       const int bf16 = p.fft_mode == MOFF_FFT_SPLIT_BF16;
       const uint16_t *mtab = reinterpret_cast<const uint16_t *>(ws(p, p.ws_mfma));
       {
-        ProfScope ps(p, st, 0, cs);
+        ProfScope ps(p, rs, 0, cs);
         const int rgrid = moff::rows_xcd_grid(p, b, tgroups);
         if (split)
-          HIP_TRY(moff::launch_rows_mfma(bf16, a, mtab, rgrid, st), "row pass");
+          HIP_TRY(moff::launch_rows_mfma(bf16, a, mtab, rgrid, rs), "row pass");
         else
-          HIP_TRY(moff::launch_rows(b.n, p.n_pol, moff::ROW_MODE_FUSED, jones, a, rgrid, lds, st), "row pass");
+          HIP_TRY(moff::launch_rows(b.n, p.n_pol, moff::ROW_MODE_FUSED, jones, a, rgrid, lds, rs), "row pass");
         HIP_TRY(ps.done(), "profile event");
       }
       if (d_tap) {
@@ -222,7 +253,11 @@ moff_status enqueue_two_pass(moff::Plan &p, const void *d_volt, int64_t n_t, voi
         ta.n_chan = p.n_chan;
         ta.n_tap = p.n_tap;
         ta.P = p.n_pol;
-        HIP_TRY(moff::launch_tap(ta, st), "tap");
+        HIP_TRY(moff::launch_tap(ta, rs), "tap");
+      }
+      if (dual) {
+        HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(p.ev_rows[slot]), rs), "row event");
+        HIP_TRY(hipStreamWaitEvent(st, static_cast<hipEvent_t>(p.ev_rows[slot]), 0), "row wait");
       }
       const int W = p.chans[b.c0].cols;
       ca.c0 = b.c0;
@@ -241,6 +276,8 @@ moff_status enqueue_two_pass(moff::Plan &p, const void *d_volt, int64_t n_t, voi
                   "column pass");
         HIP_TRY(ps.done(), "profile event");
       }
+      if (dual) HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(p.ev_cols[slot]), st), "column event");
+      ++k;
     }
   }
   return MOFF_OK;
@@ -303,6 +340,9 @@ void moff_plan_destroy(moff_plan_t plan) {
   if (!plan) return;
   drop_graphs(plan->p);
   if (plan->p.capture_stream) (void)hipStreamDestroy(static_cast<hipStream_t>(plan->p.capture_stream));
+  if (plan->p.row_stream) (void)hipStreamDestroy(static_cast<hipStream_t>(plan->p.row_stream));
+  for (void *e : {plan->p.ev_rows[0], plan->p.ev_rows[1], plan->p.ev_cols[0], plan->p.ev_cols[1], plan->p.ev_fork})
+    if (e) (void)hipEventDestroy(static_cast<hipEvent_t>(e));
   for (void *e : plan->p.ev_pool) (void)hipEventDestroy(static_cast<hipEvent_t>(e));
   delete plan;
 }

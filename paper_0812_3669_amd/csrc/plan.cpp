@@ -281,6 +281,7 @@ moff_status build_plan(const moff_plan_desc &d, Plan &p, std::string *err) {
   p.stream_slots = env_int("MOFF_STREAM_SLOTS", 3, 2, kStreamMaxSlots);
   p.spin_limit = (uint32_t)env_int("MOFF_SPIN_LIMIT", 1 << 22, 1 << 10, 1 << 28);
   p.pipeline = env_int("MOFF_PIPELINE", 0, 0, 1);
+  p.overlap = env_int("MOFF_OVERLAP", 1, 0, 1);
   int nmax = 0;
   for (int c = 0; c < C; ++c) nmax = std::max(nmax, p.chans[c].n);
   p.ws_ring = off;
@@ -325,8 +326,9 @@ size_t layout_blocks(Plan &p, int t_block, int chans_per_block, int t_group) {
     for (int c = b.c0; c < b.c1; ++c) s += (size_t)p.n_pol * p.chans[c].n * p.chans[c].n * 8;
     hmax = std::max(hmax, s * (size_t)p.t_block);
   }
-  p.ws_h_bytes = hmax;
-  p.ws_total = align256(p.ws_h + hmax);
+  p.ws_h_bytes = align256(hmax);
+  // two buffers when the row pass of the next block overlaps the column pass of this one
+  p.ws_total = align256(p.ws_h + p.ws_h_bytes * (p.overlap ? 2 : 1));
   return p.ws_total;
 }
 

@@ -135,7 +135,8 @@ class Scheduler:
     """Admission by HBM budget and slots, arrival-order queue, one time block per active job per round."""
 
     def __init__(self, executor, hbm_budget: int, max_slots: int = 8, block: int = 64,
-                 keep_results: bool = False):
+                 keep_results: bool = False, progress=None):
+        self.progress = progress        # optional callable(completed, total), called as jobs complete
         self.ex = executor
         self.budget = hbm_budget
         self.max_slots = max_slots
@@ -158,17 +159,18 @@ class Scheduler:
             while i < len(pending) and pending[i].arrival <= now:
                 spec = pending[i]
                 i += 1
-                need = self.ex.hbm(spec, self.block)
-                if need > self.budget:
-                    st.rejected += 1          # can never fit: reject at once
-                    if hasattr(self.ex, "discard"):
-                        self.ex.discard(spec)
-                    continue
+                self.ex.prefetch(spec, self.block)   # host set-up (instrument, plan) starts in the background
                 queue.append(spec)
-            # admit in arrival order while a slot and memory are free
-            while queue and len(active) < self.max_slots:
+            # admit in arrival order while a slot and memory are free; a job whose set-up is still running holds
+            # the head of the queue; one that can never fit is rejected when it reaches the head
+            while queue and len(active) < self.max_slots and self.ex.ready(queue[0]):
                 spec = queue[0]
                 need = self.ex.hbm(spec, self.block)
+                if need > self.budget:
+                    queue.pop(0)
+                    st.rejected += 1
+                    self.ex.discard(spec)
+                    continue
                 if used + need > self.budget:
                     break
                 queue.pop(0)
@@ -179,7 +181,9 @@ class Scheduler:
                 st.admitted += 1
             st.peak_concurrent = max(st.peak_concurrent, len(active))
             if not active:
-                if i < len(pending):
+                if queue:
+                    self.ex.sleep(0.001)            # the head job's set-up is still running
+                elif i < len(pending):
                     wait = t_start + pending[i].arrival - self.ex.now()
                     if wait > 0:
                         self.ex.sleep(wait)
@@ -197,6 +201,8 @@ class Scheduler:
                 js.finished = self.ex.now() - t_start
                 st.latencies.append(js.finished - js.spec.arrival)
                 st.channel_samples += js.spec.channel_samples
+                if self.progress:
+                    self.progress(len(st.latencies), len(pending))
                 if self.keep:
                     st.results[js.spec.job_id] = img
                 used -= js.hbm
@@ -227,6 +233,15 @@ class ModelExecutor:
     def hbm(self, spec, block):
         return int(hbm_bytes(spec, block) * self.hbm_scale)
 
+    def prefetch(self, spec, block):
+        pass
+
+    def ready(self, spec):
+        return True
+
+    def discard(self, spec):
+        pass
+
     def start(self, spec, block):
         self.started.append(spec.job_id)
         return {"spec": spec}
@@ -246,17 +261,23 @@ class ModelExecutor:
 class GpuExecutor:
     """Runs each job through the C ABI on its own stream; voltages are drawn per block on the device.
 
-    ``hbm`` builds the job's plan (host only) the first time it is asked, so admission uses the exact device
-    footprint: plan workspace + accumulator + image + kernels + one block of voltages.  Kernels are cached on
-    the device per array shape while a job of that shape is active.
+    A job's host set-up (its instrument's kernels, cached per array shape, and its plan) starts on a worker
+    thread when it arrives, so it overlaps the device work of the jobs already running (numpy and the plan
+    builder release the interpreter lock).  Admission uses the exact device footprint of the built plan:
+    workspace + accumulator + image + kernels + one block of voltages.
     """
 
-    def __init__(self, device="cuda:0", keep_plans: int = 64):
+    def __init__(self, device="cuda:0", workers: int = 8):
+        import threading
         import torch
+        from concurrent.futures import ThreadPoolExecutor
         self.torch = torch
         self.device = torch.device(device)
-        self._plans = {}
-        self._sites = {}
+        self._pool = ThreadPoolExecutor(max_workers=workers)
+        self._lock = threading.Lock()
+        self._plans = {}          # job id -> future of the plan
+        self._sites = {}          # array shape -> future of the instrument (geometry, gains, kernels)
+        self._site_dev = {}       # array shape -> [device kernels, active users]
 
     def now(self):
         return time.perf_counter()
@@ -267,25 +288,50 @@ class GpuExecutor:
     def advance_to(self, t):
         self.sleep(t - self.now())
 
-    def _site(self, spec):
+    @staticmethod
+    def _make_site(spec):
         from . import synth
+        scfg = spec.site_config()
+        geo = synth.geometry(scfg)
+        g = synth.gains(scfg)
+        return {"geo": geo, "g": g, "kern_np": synth.kernels(geo, g, 2)}
+
+    def _site(self, spec):
+        """The instrument of this job's shape: the first thread to ask builds it (never a nested pool task, so
+        workers cannot all block waiting on each other); the others wait for its result."""
+        from concurrent.futures import Future
         key = (spec.n_ant, spec.n_chan, spec.grid_n)
-        if key not in self._sites:
-            scfg = spec.site_config()
-            geo = synth.geometry(scfg)
-            g = synth.gains(scfg)
-            self._sites[key] = {"geo": geo, "g": g, "kern_np": synth.kernels(geo, g, 2), "kern": None, "users": 0}
-        return self._sites[key]
+        with self._lock:
+            fut = self._sites.get(key)
+            mine = fut is None
+            if mine:
+                fut = self._sites[key] = Future()
+        if mine:
+            try:
+                fut.set_result(self._make_site(spec))
+            except BaseException as e:  # pragma: no cover - surfaced to every waiter
+                fut.set_exception(e)
+        return fut.result()
+
+    def _prepare(self, spec, block):
+        from . import api
+        site = self._site(spec)
+        fft = {"fp32": api.FFT_FP32, "split_fp16": api.FFT_SPLIT_FP16}[spec.fft_mode]
+        return api.plan_for(spec.site_config(), site["geo"], fft_mode=fft, time_block=block,
+                            chans_per_block=spec.chans_per_launch(block))
+
+    def prefetch(self, spec, block):
+        with self._lock:
+            if spec.job_id not in self._plans:
+                self._plans[spec.job_id] = self._pool.submit(self._prepare, spec, block)
+
+    def ready(self, spec):
+        fut = self._plans.get(spec.job_id)
+        return fut is not None and fut.done()
 
     def _plan(self, spec, block):
-        from . import api
-        if spec.job_id not in self._plans:
-            site = self._site(spec)
-            fft = {"fp32": api.FFT_FP32, "split_fp16": api.FFT_SPLIT_FP16}[spec.fft_mode]
-            plan = api.plan_for(spec.site_config(), site["geo"], fft_mode=fft, time_block=block,
-                                chans_per_block=spec.chans_per_launch(block))
-            self._plans[spec.job_id] = plan
-        return self._plans[spec.job_id]
+        self.prefetch(spec, block)
+        return self._plans[spec.job_id].result()
 
     def hbm(self, spec, block):
         plan = self._plan(spec, block)
@@ -303,19 +349,21 @@ class GpuExecutor:
         plan = self._plan(spec, block)
         cfg = spec.config()
         sk = synth.sky(cfg)
+        key = (spec.n_ant, spec.n_chan, spec.grid_n)
         stream = torch.cuda.Stream(device=self.device)
         with torch.cuda.stream(stream):
-            if site["kern"] is None:
-                site["kern"] = torch.from_numpy(site["kern_np"]).to(self.device)
-            site["users"] += 1
+            dev = self._site_dev.get(key)
+            if dev is None:
+                dev = self._site_dev[key] = [torch.from_numpy(site["kern_np"]).to(self.device), 0]
+            dev[1] += 1
             plan.bind(self.device, stream=stream)
-            plan.set_kernels(site["kern"], stream=stream)
+            plan.set_kernels(dev[0], stream=stream)
             acc = plan.new_accumulator()
             gen = synth.DeviceVoltages(cfg, site["geo"], site["g"], sk, self.device, chunk=block)
             vbuf = torch.empty((block, cfg.n_chan, cfg.n_ant, cfg.n_pol, 2), dtype=torch.int8, device=self.device)
         ev = torch.cuda.Event()
         return {"spec": spec, "plan": plan, "acc": acc, "gen": gen, "vbuf": vbuf, "stream": stream, "ev": ev,
-                "site": site, "block": block}
+                "site_key": key, "block": block}
 
     def step(self, h, t0, nt):
         torch = self.torch
@@ -334,9 +382,9 @@ class GpuExecutor:
         with torch.cuda.stream(h["stream"]):
             img = h["plan"].read_image(h["acc"], n_samples=h["spec"].n_time, stream=h["stream"], split=False)
         h["stream"].synchronize()
-        site = h["site"]
-        site["users"] -= 1
-        if site["users"] == 0:
-            site["kern"] = None                 # free the device copy; the host copy stays cached
+        dev = self._site_dev[h["site_key"]]
+        dev[1] -= 1
+        if dev[1] == 0:
+            del self._site_dev[h["site_key"]]   # free the device copy; the host copy stays cached
         self._plans.pop(h["spec"].job_id, None)
         return img

@@ -84,6 +84,7 @@ def kernels(geo: Geometry, g: np.ndarray, n_pol: int) -> np.ndarray:
     C, A = len(geo.freqs_hz), geo.ant_xy_m.shape[0]
     out = np.empty((C, A, n_pol, K, K), dtype=np.complex64)
     taps = np.arange(K, dtype=np.float64)
+    g64 = g[:, :n_pol].astype(np.complex64)
     for c in range(C):
         lam_cells = geo.freqs_hz[c] / C_LIGHT / geo.cell_lambda
         X = geo.ant_xy_m[:, 0] * lam_cells + geo.grid_n[c] / 2
@@ -91,7 +92,7 @@ def kernels(geo: Geometry, g: np.ndarray, n_pol: int) -> np.ndarray:
         dx = np.floor(X)[:, None] - K // 2 + 1 + taps[None, :] - X[:, None]   # [A, K]
         dy = np.floor(Y)[:, None] - K // 2 + 1 + taps[None, :] - Y[:, None]
         env = np.exp(-(dy[:, :, None] ** 2 + dx[:, None, :] ** 2) / 2.0)      # [A, K(y), K(x)]
-        out[c] = (g[:, :, None, None] * env[:, None, :, :]).astype(np.complex64)
+        np.multiply(g64[:, :, None, None], env.astype(np.float32)[:, None, :, :], out=out[c])
     return out
 
 

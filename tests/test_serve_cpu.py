@@ -63,3 +63,20 @@ def test_job_site_shared_by_shape_and_launch_cap():
     assert big.fft_mode == "fp32" and a.fft_mode == "split_fp16"
     cpl = big.chans_per_launch(64)
     assert cpl >= 1 and 64 * cpl * 2 * 512 ** 2 * 8 <= (1 << 30)
+
+
+def test_gpu_executor_prepares_jobs_in_background():
+    """Host set-up of queued jobs runs on worker threads (fewer workers than jobs, jobs sharing instruments)
+    and completes: no worker waits on work queued behind it.  Plans are host-only, so this runs on the CPU."""
+    import time
+    ex = serve.GpuExecutor("cuda:0", workers=2)
+    specs = [serve.JobSpec(j, 0.0, 256, 16, 64, 128 if j % 2 else 64 + 64, "fp32", seed=j) for j in range(6)]
+    for sp in specs:
+        ex.prefetch(sp, 64)
+    t0 = time.time()
+    while not all(ex.ready(sp) for sp in specs):
+        assert time.time() - t0 < 60, "set-up did not finish"
+        time.sleep(0.01)
+    sizes = [ex.hbm(sp, 64) for sp in specs]
+    assert all(s > 0 for s in sizes)
+    assert len(ex._sites) == 1          # one instrument shape shared by every job
