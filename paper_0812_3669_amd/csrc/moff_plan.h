@@ -72,7 +72,7 @@ struct Plan {
   int32_t t_block = 16;                 // samples per fused launch block
   int32_t t_group = 4;                  // samples per row-pass workgroup
   int32_t pipeline = 0;                 // moff_pipeline of the fused path
-  int32_t overlap = 1;                  // two-pass form: row pass of block k + 1 overlaps column pass of block k
+  int32_t overlap = 0;                  // two-pass form: row pass of block k + 1 overlaps column pass of block k (MOFF_OVERLAP=1)
   void *row_stream = nullptr;           // hipStream_t of the overlapped row passes (created on first use)
   void *ev_rows[2] = {nullptr, nullptr}, *ev_cols[2] = {nullptr, nullptr}, *ev_fork = nullptr;
   int32_t stream_slots = 3;             // ring slots per XCD (streaming form)

@@ -105,7 +105,7 @@ moff_status build_plan(const moff_plan_desc &d, Plan &p, std::string *err) {
   if (d.chans_per_block < 0 || d.time_group < 0) return fail(err, MOFF_E_INVALID, "launch shape must be >= 0");
   // defaults: the shape the autotuner picks for the 2048-antenna, 256^2 workload on MI355X
   const int tb = d.time_block > 0 ? d.time_block : env_int("MOFF_T_BLOCK", 64, 1, 4096);
-  const int tg = d.time_group > 0 ? d.time_group : env_int("MOFF_T_GROUP", 4, 1, 4096);
+  const int tg = d.time_group > 0 ? d.time_group : env_int("MOFF_T_GROUP", 8, 1, 4096);
   const int cpb = d.chans_per_block > 0 ? d.chans_per_block : env_int("MOFF_CHANS_PER_BLOCK", 64, 1, 1 << 20);
 
   // ---- per-channel grid size and footprints ------------------------------------------------------------
@@ -281,7 +281,7 @@ moff_status build_plan(const moff_plan_desc &d, Plan &p, std::string *err) {
   p.stream_slots = env_int("MOFF_STREAM_SLOTS", 3, 2, kStreamMaxSlots);
   p.spin_limit = (uint32_t)env_int("MOFF_SPIN_LIMIT", 1 << 22, 1 << 10, 1 << 28);
   p.pipeline = env_int("MOFF_PIPELINE", 0, 0, 1);
-  p.overlap = env_int("MOFF_OVERLAP", 1, 0, 1);
+  p.overlap = env_int("MOFF_OVERLAP", 0, 0, 1);
   int nmax = 0;
   for (int c = 0; c < C; ++c) nmax = std::max(nmax, p.chans[c].n);
   p.ws_ring = off;
