@@ -1,0 +1,37 @@
+// Host-only driver of the plan builder (plan.cpp) for the sanitizer test: builds plans for several layouts
+// (fixed and automatic grid sizes, taps, a single antenna, a footprint leaving the grid) with no HIP code.
+#include "moff_plan.h"
+#include <cstdio>
+#include <cmath>
+#include <random>
+#include <vector>
+int run(int A, int C, int n, int K, double disk, int P, int ntap, int seed) {
+  std::mt19937_64 rng(seed);
+  std::uniform_real_distribution<double> U(0, 1);
+  double c = 299792458.0, fref = 130e6, Dm = disk * c / fref;
+  std::vector<double> xy(2 * A), f(C);
+  for (int a = 0; a < A; ++a) { double r = 0.5 * Dm * sqrt(U(rng)), ph = 2 * M_PI * U(rng); xy[2*a] = r*cos(ph); xy[2*a+1] = r*sin(ph); }
+  for (int i = 0; i < C; ++i) f[i] = 100e6 + (i + 0.5) * 30e6 / C;
+  std::vector<int> gn(C, n);
+  moff_plan_desc d{}; d.n_ant = A; d.n_pol = P; d.n_chan = C; d.ksize = K; d.ant_xy_m = xy.data(); d.freq_hz = f.data();
+  d.grid_n = n > 0 ? gn.data() : nullptr; d.cell_lambda = 1.0; d.n_tap = ntap;
+  moff::Plan p; std::string err;
+  int s = moff::build_plan(d, p, &err);
+  if (s) { printf("A=%d C=%d n=%d K=%d: status %d (%s)\n", A, C, n, K, s, err.c_str()); return s; }
+  long taps = 0;
+  for (auto m : p.grp_meta) taps += (m != moff::kEmptyTap);
+  printf("A=%d C=%d n=%d K=%d P=%d: bands %zu groups %lld taps %ld ws %zu\n", A, C, n, K, P, p.bands.size(), (long long)p.n_groups, taps, p.ws_total);
+  for (int tb : {1, 8, 64}) for (int cpb : {1, 7, 64}) moff::layout_blocks(p, tb, cpb, 4);
+  return 0;
+}
+int main() {
+  int bad = 0;
+  bad |= run(64, 1, 64, 4, 30, 1, 0, 1);
+  bad |= run(256, 8, 128, 4, 60, 2, 2, 2);
+  bad |= run(2048, 4, 256, 4, 200, 2, 8, 3);
+  bad |= run(512, 6, 0, 6, 120, 2, 0, 4);      // automatic grid sizes
+  bad |= run(1, 1, 32, 8, 1, 2, 1, 5);
+  bad |= run(300, 2, 512, 2, 400, 1, 0, 6);
+  run(100, 1, 32, 4, 200, 2, 0, 7);            // footprints leave the grid: an error, not a crash
+  return bad;
+}

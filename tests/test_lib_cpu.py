@@ -179,3 +179,26 @@ def test_tap_validation_and_sizes():
     # taps need a bound plan made with n_tap > 0
     assert taps.lib.moff_correlate_tap(taps._h, C.c_void_p(1), 1, C.c_void_p(1), C.c_void_p(1), None) == 5
     assert plain.lib.moff_cal_accumulate(plain._h, C.c_void_p(1), C.c_void_p(1), 1, C.c_void_p(1), None) == 5
+
+
+def test_plan_builder_under_host_sanitizers(tmp_path):
+    """The host plan builder compiled with g++ -fsanitize=address,undefined (host code only, no HIP) builds
+    plans for several layouts without a memory or undefined-behaviour report."""
+    import os
+    import shutil
+    import subprocess
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not available")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    exe = str(tmp_path / "plan_sanitizer")
+    cmd = [gxx, "-O1", "-g", "-std=c++17", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+           "-I" + os.path.join(root, "include"), "-I" + os.path.join(root, "paper_0812_3669_amd", "csrc"),
+           os.path.join(root, "tests", "plan_sanitizer_driver.cpp"),
+           os.path.join(root, "paper_0812_3669_amd", "csrc", "plan.cpp"), "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-2000:]
+    r = subprocess.run([exe], capture_output=True, text=True, env=dict(os.environ, ASAN_OPTIONS="detect_leaks=1"))
+    assert r.returncode == 0, (r.stdout[-2000:], r.stderr[-2000:])
+    assert "runtime error" not in r.stderr and "AddressSanitizer" not in r.stderr
+    assert "leaves the 32^2 grid" in r.stdout
