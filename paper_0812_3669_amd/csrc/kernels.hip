@@ -585,7 +585,7 @@ __device__ __forceinline__ void col_group(const ColArgs &a, int c, int cg, int t
 
 // Fused / staged column pass: one workgroup per (channel, column group), samples split over gridDim.y.
 template <int N, int P, int W, int MODE, int ACC>
-__global__ __launch_bounds__(kThreads) void k_cols(ColArgs a) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_cols(ColArgs a) {
   extern __shared__ float4 smem4[];
   float2 *buf = reinterpret_cast<float2 *>(smem4);   // [P][W][TS]
   float2 *tws = buf + P * W * Pipe<N>::TS;            // [2N] twiddle tables
@@ -608,7 +608,8 @@ __global__ __launch_bounds__(kThreads) void k_cols(ColArgs a) {
     else
       return a.in + (int64_t)t * a.sample_stride + (int64_t)P * a.chans[c].pix_off;
   };
-  col_group<N, P, W, MODE, ACC, LD_STREAM, true>(a, c, cg, t_begin, t_end, buf, tws, src, [](int) {}, [](int) {});
+  // the next sample's first-stage inputs are prefetched where the registers allow it (up to 256-point columns)
+  col_group<N, P, W, MODE, ACC, LD_STREAM, (N <= 256)>(a, c, cg, t_begin, t_end, buf, tws, src, [](int) {}, [](int) {});
 }
 
 // ------------------------------------------------------------------------------------------------------------
