@@ -14,8 +14,9 @@ constexpr int kMaxLds = 160 * 1024;   // LDS per CU on CDNA4
 
 // Rows per band of the row pass (must match band_rows_for in the plan).
 constexpr int band_rows_ce(int n, int P) {
+  const int limit = (n & (n - 1)) == 0 ? 32768 : 16384;
   int h = 16;
-  while (h > 4 && P * h * n * 8 > 32768) h /= 2;
+  while (h > 4 && P * h * n * 8 > limit) h /= 2;
   return h;
 }
 

@@ -220,7 +220,9 @@ __device__ __forceinline__ void row_band(const RowArgs &a, int band, int t_lo, i
   constexpr int TS = row_stride(N);   // even: rows start on 16-byte boundaries
   static_assert(TS >= N + PP::RMAX - 1, "row stride too small for the padded layout");
   constexpr int HB = band_rows_ce(N, P);             // rows per band
-  constexpr int GCH = 8;                             // tap groups whose loads are issued together
+  // tap groups whose loads are issued together: 8 where LDS bounds the occupancy anyway (power-of-two n), 4 for
+  // mixed-radix n, whose occupancy is bounded by registers
+  constexpr int GCH = (N & (N - 1)) == 0 ? 8 : 4;
 
   const Band *bp = a.bands + band;
   struct {

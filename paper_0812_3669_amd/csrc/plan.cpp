@@ -39,10 +39,13 @@ bool fft_size_supported(int n) {
   return false;
 }
 
-// Rows per band of the row pass: the band grid (P x rows x n complex64) stays within 32 KB of LDS.
+// Rows per band of the row pass: the band grid (P x rows x n complex64) stays within 32 KB of LDS for
+// power-of-two n and within 16 KB for mixed-radix n (their three-stage row transforms hold more registers, and
+// shorter bands measured faster there).
 int band_rows_for(int n, int P) {
+  const size_t limit = (n & (n - 1)) == 0 ? 32768 : 16384;
   int h = 16;
-  while (h > 4 && (size_t)P * h * n * 8 > 32768) h /= 2;
+  while (h > 4 && (size_t)P * h * n * 8 > limit) h /= 2;
   return h;
 }
 
