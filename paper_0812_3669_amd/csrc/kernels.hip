@@ -610,8 +610,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     else
       return a.in + (int64_t)t * a.sample_stride + (int64_t)P * a.chans[c].pix_off;
   };
-  // the next sample's first-stage inputs are prefetched where the registers allow it (up to 256-point columns)
-  col_group<N, P, W, MODE, ACC, LD_STREAM, (N <= 256)>(a, c, cg, t_begin, t_end, buf, tws, src, [](int) {}, [](int) {});
+  // the next sample's first-stage inputs are prefetched for columns of up to 160 points; longer columns need the
+  // registers for occupancy (at 192 the prefetch costs a wave per SIMD, at 256 it gains nothing)
+  col_group<N, P, W, MODE, ACC, LD_STREAM, (N <= 160)>(a, c, cg, t_begin, t_end, buf, tws, src, [](int) {}, [](int) {});
 }
 
 // ------------------------------------------------------------------------------------------------------------
