@@ -56,6 +56,60 @@ def _traffic(kernel: str, launch_cs: int):
     return k.get("bytes_per_launch")
 
 
+TRAFFIC_COMMANDS = [
+    "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_FETCH_SIZE -o run -- python3 -u bench.py "
+    "--time 512 --steps 1 --warmup 1 --no-cpu-baseline --eager",
+    "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_WRITE_SIZE -o run -- python3 -u bench.py "
+    "--time 512 --steps 1 --warmup 1 --no-cpu-baseline --eager",
+    "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmccopy_FETCH_SIZE -o run -- python3 -u bench.py "
+    "--calibrate-copy",
+    "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmccopy_WRITE_SIZE -o run -- python3 -u bench.py "
+    "--calibrate-copy",
+]
+
+
+def write_traffic(pmc_dir: str, launch_cs: int = 4096, out_path: str | None = None) -> dict:
+    """Reduces the four rocprofv3 --pmc runs of ``TRAFFIC_COMMANDS`` (CSV output under ``pmc_dir``) to
+    ``profiles/traffic.json``: per fused-path kernel, FETCH_SIZE and WRITE_SIZE (KiB per dispatch, averaged over
+    dispatches), each scaled by copy bytes / counter reading of the 1 GiB device copy; keyed by the kernel
+    sources' hash.  The default launch shape (64 samples x 64 channels) gives ``launch_cs`` channel-samples."""
+    import collections
+    import csv
+
+    def per_dispatch(sub):
+        per = collections.defaultdict(lambda: collections.defaultdict(float))
+        with open(os.path.join(pmc_dir, sub, "run_counter_collection.csv")) as fh:
+            for r in csv.DictReader(fh):
+                per[r["Kernel_Name"]][r["Dispatch_Id"]] += float(r["Counter_Value"])
+        return {k: (len(v), sum(v.values()) / len(v)) for k, v in per.items()}
+
+    def pick(table, prefix):
+        hits = [(n, v) for k, (n, v) in table.items() if k.startswith(prefix)]
+        if not hits:
+            raise SystemExit(f"bench: no dispatch of {prefix!r} under {pmc_dir}")
+        return max(hits)   # the instantiation with the most dispatches
+
+    copy_kib = (1 << 30) / 1024
+    scale = {c: copy_kib / pick(per_dispatch("pmccopy_" + c), "__amd_rocclr_copyBuffer")[1]
+             for c in ("FETCH_SIZE", "WRITE_SIZE")}
+    fetch, write = per_dispatch("pmc_FETCH_SIZE"), per_dispatch("pmc_WRITE_SIZE")
+    kernels = {}
+    for k in ("k_rows", "k_cols"):
+        f = pick(fetch, f"void moff::{k}<")[1]
+        w = pick(write, f"void moff::{k}<")[1]
+        kernels[k] = {"channel_samples_per_launch": launch_cs, "fetch_kib": round(f), "write_kib": round(w),
+                      "bytes_per_launch": round((f * scale["FETCH_SIZE"] + w * scale["WRITE_SIZE"]) * 1024)}
+    d = {"src_hash": _src_hash(),
+         "note": "rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE per dispatch (KiB), each scaled by what the counter reads "
+                 "for a plain 1 GiB device copy (FETCH x%.3f, WRITE x%.3f)" % (scale["FETCH_SIZE"],
+                                                                              scale["WRITE_SIZE"]),
+         "commands": TRAFFIC_COMMANDS, "kernels": kernels}
+    with open(out_path or os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
+        json.dump(d, fh, indent=1)
+        fh.write("\n")
+    return d
+
+
 def cpu_baseline(cfg, geo, kern_np, volts_dev, budget_s: float = 12.0):
     """The FP64 oracle timed on this host on a bounded sample: channel 0, growing sample counts."""
     import numpy as np
@@ -128,6 +182,7 @@ def main():
     ap.add_argument("--autotune", action="store_true", help="tune the launch shape on the first 256 samples")
     ap.add_argument("--eager", action="store_true", help="launch kernel by kernel instead of replaying a HIP graph")
     ap.add_argument("--calibrate-copy", action="store_true", help="run a 1 GiB device copy (PMC calibration)")
+    ap.add_argument("--write-traffic", metavar="DIR", help="write profiles/traffic.json from the PMC runs under DIR")
     ap.add_argument("--pipeline", choices=["two_pass", "stream"], default="two_pass",
                     help="row/column exchange of the fused path: two kernels through HBM, or one persistent "
                          "launch per grid size streaming through each XCD's cache")
@@ -138,6 +193,9 @@ def main():
                          "50-200 MHz with per-channel grid sizes (128^2..384^2), 6x6 kernels")
     args = ap.parse_args()
 
+    if args.write_traffic:
+        print(json.dumps(write_traffic(args.write_traffic), indent=1))
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs the MOFF hot path on one GPU only (asked for --gpus {args.gpus}); "
               "multi-GPU sharding is a design note, not part of this build.", file=sys.stderr)
@@ -154,7 +212,21 @@ def main():
         for _ in range(3):
             b.copy_(a)
         torch.cuda.synchronize()
-        print(json.dumps({"calibrate_copy_bytes": a.numel() * 4, "launches": 3}))
+        # what plain device kernels reach on this GPU's HBM: the same copy (read + write), a fill (write only)
+        # and a sum (read only), 10 launches each, timed with events
+        nbytes = a.numel() * 4
+        rates = {}
+        for name, fn, moved in (("copy", lambda: b.copy_(a), 2 * nbytes), ("fill", lambda: b.fill_(0.5), nbytes),
+                                ("read", lambda: torch.sum(a), nbytes)):
+            fn()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(10):
+                fn()
+            e1.record()
+            e1.synchronize()
+            rates[name] = round(10 * moved / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+        print(json.dumps({"calibrate_copy_bytes": nbytes, "launches": 3, "hbm_gbps": rates}))
         return
 
     if args.workload == "serving":
