@@ -506,7 +506,7 @@ __device__ __forceinline__ void col_group(const ColArgs &a, int c, int cg, int t
 #pragma unroll
     for (int s = 0; s < MBL; ++s) {
       const int b0 = threadIdx.x + s * kThreads;
-      const bool valid = b0 < NSL;
+      const bool valid = NSL % kThreads == 0 || b0 < NSL;   // the first form: every lane holds a butterfly
       const int b = valid ? b0 : 0;
       const int p = P == 2 ? (b & 1) : 0;
       const int rest = P == 2 ? (b >> 1) : b;
@@ -521,14 +521,16 @@ __device__ __forceinline__ void col_group(const ColArgs &a, int c, int cg, int t
         for (int r = 0; r < RL; ++r) {
           const float2 mine = x[r];
           if constexpr (P == 2) {
+            // the X lane takes Re(X conj Y) = Re(Y conj X) and the Y lane Im(X conj Y) = Re(X conj(i Y)): both
+            // are Re(other conj(u)) with u = mine on the X lane and i mine on the Y lane
             const float2 other = make_float2(swap_pair(mine.x), swap_pair(mine.y));
-            const float2 ex = p == 0 ? mine : other, ey = p == 0 ? other : mine;
+            const float2 u = p == 0 ? mine : make_float2(-mine.y, mine.x);
             if (valid) {
-              acc[s][r][0] += mine.x * mine.x + mine.y * mine.y;                         // XX or YY
-              acc[s][r][1] += p == 0 ? ex.x * ey.x + ex.y * ey.y : ex.y * ey.x - ex.x * ey.y;  // Re / Im XY
+              acc[s][r][0] = fmaf(mine.y, mine.y, fmaf(mine.x, mine.x, acc[s][r][0]));   // XX or YY
+              acc[s][r][1] = fmaf(other.y, u.y, fmaf(other.x, u.x, acc[s][r][1]));      // Re XY or Im XY
             }
           } else {
-            if (valid) acc[s][r][0] += mine.x * mine.x + mine.y * mine.y;
+            if (valid) acc[s][r][0] = fmaf(mine.y, mine.y, fmaf(mine.x, mine.x, acc[s][r][0]));
           }
         }
       } else {

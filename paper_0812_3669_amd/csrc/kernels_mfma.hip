@@ -182,11 +182,12 @@ __global__ __launch_bounds__(kThreads) void k_cols_mfma(ColArgs a, const uint16_
     __syncthreads();
     if (t + 1 < a.t0 + a.nt) load_tile(t + 1);
     fft256x16_mfma<BF16>(xs, MTS, ys, mats, [&](int, int, float2 v, int jj, int i) {
-      // lanes t and t ^ 8 hold the two pols of one pixel
+      // lanes t and t ^ 8 hold the two pols of one pixel; the X lane takes Re(X conj Y) = Re(o conj(v)), the Y
+      // lane Im(X conj Y) = Re(o conj(i v))
       const float2 o = make_float2(__shfl_xor(v.x, 8), __shfl_xor(v.y, 8));
-      const float2 ex = p == 0 ? v : o, ey = p == 0 ? o : v;
-      acc[jj][i][0] += v.x * v.x + v.y * v.y;
-      acc[jj][i][1] += p == 0 ? ex.x * ey.x + ex.y * ey.y : ex.y * ey.x - ex.x * ey.y;
+      const float2 u = p == 0 ? v : make_float2(-v.y, v.x);
+      acc[jj][i][0] = fmaf(v.y, v.y, fmaf(v.x, v.x, acc[jj][i][0]));
+      acc[jj][i][1] = fmaf(o.y, u.y, fmaf(o.x, u.x, acc[jj][i][1]));
     });
   }
 
