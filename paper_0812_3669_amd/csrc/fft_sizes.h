@@ -14,4 +14,10 @@ constexpr int fft_radix_max(int n) {
 // LDS stride (complex elements) of one row in the row pass: the padded inter-stage layout needs n + R - 1.
 constexpr int row_stride(int n) { return n + fft_radix_max(n); }
 
+// Whether the row pass of length n copies its band's voltages into an LDS table once per sample (tap-group
+// metadata then holds the antenna's position in the band list) or gathers them per tap from the voltage row
+// (metadata holds the antenna index).  At 320 and 384 the table's registers cost a wave per SIMD, which outweighs
+// the coalesced loads.
+constexpr bool row_stages_volts(int n) { return n != 320 && n != 384; }
+
 }  // namespace moff

@@ -39,6 +39,8 @@ struct RowArgs {
   const void *volt;
   int volt_fmt;
   const uint32_t *meta;
+  const int32_t *band_ant;   // band antenna lists (Band::ant_off, ant_cnt)
+  int band_ants_max;         // longest list: entries of the LDS voltage table
   const float2 *wk;
   const float2 *tw;
   float2 *io;                // fused: H of the launch block; staged: grid buffer
@@ -128,9 +130,10 @@ struct StreamArgs {
   uint32_t spin_limit;
 };
 
-// Voltages of G taps at once (antenna = meta >> 16; empty taps give 0).  The format branch is uniform and outside
-// the unrolled loads, and the loads are unconditional (an empty tap reads antenna 0), so all G are issued before
-// the first is used.
+// Voltages of G taps at once from a voltage row laid out like the caller's (record = meta >> 16; empty taps give
+// 0): the row pass reads its band's LDS voltage table this way.  The format branch is uniform and outside the
+// unrolled reads, and the reads are unconditional (an empty tap reads record 0), so all G are issued before the
+// first is used.
 template <int P, int G>
 __device__ __forceinline__ void load_volts(const void *row, int fmt, const uint32_t (&m)[G], float2 (&e)[G][P]) {
   int ant[G];
@@ -169,6 +172,51 @@ __device__ __forceinline__ void load_volts(const void *row, int fmt, const uint3
 #pragma unroll
       for (int k = 0; k < G; ++k) e[k][0] = m[k] != kEmptyTap ? w[k] : make_float2(0.f, 0.f);
     }
+  }
+}
+
+// Bytes of one antenna's voltages for one (sample, channel): P pols of (re, im), int8 (format 0) or float.
+__host__ __device__ constexpr int volt_rec_bytes(int P, int fmt) { return P * (fmt == 0 ? 2 : 8); }
+
+// Bytes of the row pass's LDS voltage table: one record per antenna of the longest band list, 16-byte aligned.
+__host__ __device__ constexpr size_t volt_table_bytes(int band_ants, int P, int fmt) {
+  return ((size_t)band_ants * volt_rec_bytes(P, fmt) + 15) / 16 * 16;
+}
+
+// One antenna's voltage record (2, 4, 8 or 16 bytes) as a single load, in the low words of a uint4.
+template <int P>
+__device__ __forceinline__ uint4 fetch_volt_rec(const char *row, int fmt, int ant) {
+  uint4 v = make_uint4(0u, 0u, 0u, 0u);
+  if (fmt == 0) {
+    if constexpr (P == 2)
+      v.x = reinterpret_cast<const uint32_t *>(row)[ant];
+    else
+      v.x = reinterpret_cast<const uint16_t *>(row)[ant];
+  } else {
+    if constexpr (P == 2) {
+      v = reinterpret_cast<const uint4 *>(row)[ant];
+    } else {
+      const uint2 w = reinterpret_cast<const uint2 *>(row)[ant];
+      v.x = w.x;
+      v.y = w.y;
+    }
+  }
+  return v;
+}
+
+// Writes record i of the LDS voltage table (the layout of one voltage row: load_volts reads it back).
+template <int P>
+__device__ __forceinline__ void put_volt_rec(char *vtab, int fmt, int i, uint4 v) {
+  if (fmt == 0) {
+    if constexpr (P == 2)
+      reinterpret_cast<uint32_t *>(vtab)[i] = v.x;
+    else
+      reinterpret_cast<uint16_t *>(vtab)[i] = (uint16_t)v.x;
+  } else {
+    if constexpr (P == 2)
+      reinterpret_cast<uint4 *>(vtab)[i] = v;
+    else
+      reinterpret_cast<uint2 *>(vtab)[i] = make_uint2(v.x, v.y);
   }
 }
 
@@ -247,7 +295,7 @@ hipError_t launch_cal_solve(const SolveArgs &a, hipStream_t st);
 enum { ROW_MODE_FUSED = 0, ROW_MODE_GRID = 1, ROW_MODE_FFT = 2 };
 enum { COL_MODE_FUSED = 0, COL_MODE_FFT = 1 };
 
-size_t rows_lds_bytes(int n, int P, int band_rows, int A, int volt_fmt);
+size_t rows_lds_bytes(int n, int P, int band_rows, int band_ants, int volt_fmt);
 size_t cols_lds_bytes(int n, int P, int W);
 hipError_t launch_rows(int n, int P, int mode, bool jones, const RowArgs &a, int grid, size_t lds, hipStream_t st);
 hipError_t launch_cols(int n, int P, int W, int mode, int accm, const ColArgs &a, int grid, int gridy, size_t lds,
@@ -260,13 +308,13 @@ hipError_t launch_pack_kernels(const float2 *kern, const float2 *phase, const in
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t st);
 hipError_t launch_unpack_debug(const void *volt, int fmt, float2 *out, int64_t count, hipStream_t st);
 hipError_t set_lds_limit_ext(const void *fn);
-size_t stream_lds_bytes(int n, int P);
-hipError_t stream_occupancy(int n, int P, int accm, bool jones, int *wgs_per_cu);
+size_t stream_lds_bytes(int n, int P, int band_ants, int volt_fmt);
+hipError_t stream_occupancy(int n, int P, int accm, bool jones, int band_ants, int volt_fmt, int *wgs_per_cu);
 hipError_t launch_stream(int n, int P, int accm, bool jones, const StreamArgs &a, hipStream_t st);
 
 // precision form (256^2 grids, two pols; kernels_mfma.hip)
 constexpr size_t kMfmaTableBytes = (size_t)17 * 2 * 3 * 64 * 8 * 2;
-size_t rows_mfma_lds_bytes();
+size_t rows_mfma_lds_bytes(int band_ants, int volt_fmt);
 size_t cols_mfma_lds_bytes();
 hipError_t launch_mfma_table(uint16_t *tab, int bf16, hipStream_t st);
 hipError_t launch_rows_mfma(int bf16, const RowArgs &a, const uint16_t *table, int grid, hipStream_t st);

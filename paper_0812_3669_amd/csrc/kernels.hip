@@ -213,7 +213,7 @@ __device__ __forceinline__ void row_stage_out(const float2 *buf, int ntr, const 
 
 template <int N, int P, int MODE, bool KJ, class Out>
 __device__ __forceinline__ void row_band(const RowArgs &a, int band, int t_lo, int t_hi, float2 *grid,
-                                         const float2 *tws, Out out) {
+                                         const float2 *tws, char *vtab, Out out) {
   static_assert(!KJ || P == 2, "Jones kernels need two pols");
   constexpr int PL = KJ ? 4 : P;                      // packed kernel planes
   using PP = Pipe<N>;
@@ -267,8 +267,30 @@ __device__ __forceinline__ void row_band(const RowArgs &a, int band, int t_lo, i
     }
   };
 
+  // voltages: thread i copies the record of the i-th antenna of the band's list (ascending) into the LDS table
+  // vtab before each sample's scatter, so the scatter reads its voltages from LDS (coalesced global loads instead
+  // of per-tap gathers).  int8 records (one register) are loaded for the next sample while this sample is
+  // transformed; float records are copied when they are staged.
+  constexpr bool SCAT = MODE == ROW_FUSED || MODE == ROW_GRID;
+  constexpr bool STAGE = SCAT && row_stages_volts(N);
+  const int bcnt = STAGE ? bp->ant_cnt : 0;
+  const int32_t *blist = a.band_ant + bp->ant_off;
+  const int my_ant = (STAGE && (int)threadIdx.x < bcnt) ? blist[threadIdx.x] : -1;
+  auto vrow_of = [&](int t) {
+    return reinterpret_cast<const char *>(a.volt) + ((int64_t)t * a.n_chan + c) * vbytes;
+  };
+  const bool pre8 = a.volt_fmt == 0 && my_ant >= 0;
+  uint32_t nxt = 0u;
+  if (pre8 && t_lo < t_hi) nxt = fetch_volt_rec<P>(vrow_of(t_lo), 0, my_ant).x;
+
   for (int t = t_lo; t < t_hi; ++t) {
-    if constexpr (MODE == ROW_FUSED || MODE == ROW_GRID) {
+    if constexpr (SCAT) {
+      if (pre8)
+        put_volt_rec<P>(vtab, 0, threadIdx.x, make_uint4(nxt, 0u, 0u, 0u));
+      else if (my_ant >= 0)
+        put_volt_rec<P>(vtab, a.volt_fmt, threadIdx.x, fetch_volt_rec<P>(vrow_of(t), a.volt_fmt, my_ant));
+      for (int i = threadIdx.x + kThreads; i < bcnt; i += kThreads)
+        put_volt_rec<P>(vtab, a.volt_fmt, i, fetch_volt_rec<P>(vrow_of(t), a.volt_fmt, blist[i]));
       // clear the band grid (16-byte stores over the whole contiguous region)
       {
         float4 *g4 = reinterpret_cast<float4 *>(grid);
@@ -279,7 +301,6 @@ __device__ __forceinline__ void row_band(const RowArgs &a, int band, int t_lo, i
       // deterministic scatter: this wavefront's tap groups, one tap per lane, 64 distinct cells per group;
       // the loads of GCH groups are issued before any of them is used
       {
-        const char *vrow = reinterpret_cast<const char *>(a.volt) + ((int64_t)t * a.n_chan + c) * vbytes;
         for (int g = 0; g < gc; g += GCH) {
           uint32_t m[GCH];
           float2 w[GCH][PL];
@@ -291,16 +312,20 @@ __device__ __forceinline__ void row_band(const RowArgs &a, int band, int t_lo, i
             for (int p = 0; p < PL; ++p)
               w[k][p] = ok ? a.wk[((g0 + g + k) * PL + p) * 64 + lane] : make_float2(0.f, 0.f);
           }
-          // voltages of the GCH groups' taps: branch-free (an empty lane reads antenna 0 and discards it), so
-          // the GCH loads are in flight together
+          // voltages of the GCH groups' taps from the LDS table or the voltage row (an empty lane reads record 0
+          // and discards it; the loads are branch-free, so all GCH are in flight together)
           float2 e[GCH][P];
-          load_volts<P, GCH>(vrow, a.volt_fmt, m, e);
+          if constexpr (STAGE)
+            load_volts<P, GCH>(vtab, a.volt_fmt, m, e);
+          else
+            load_volts<P, GCH>(vrow_of(t), a.volt_fmt, m, e);
 #pragma unroll
           for (int k = 0; k < GCH; ++k)
             if (m[k] != kEmptyTap) scatter_tap(m[k], w[k], e[k]);
         }
       }
       __syncthreads();
+      if (pre8 && t + 1 < t_hi) nxt = fetch_volt_rec<P>(vrow_of(t + 1), 0, my_ant).x;
     } else {
       // ROW_FFT: load the band's touched rows from the staged grid
       for (int i = threadIdx.x; i < ntr * N; i += kThreads) {
@@ -361,6 +386,7 @@ __global__ __launch_bounds__(kThreads) void k_rows(RowArgs a) {
   extern __shared__ float4 smem4[];
   float2 *grid = reinterpret_cast<float2 *>(smem4);  // [P][HB][TS]
   float2 *tws = grid + P * HB * TS;                  // [2N] twiddle tables
+  char *vtab = reinterpret_cast<char *>(tws + 2 * N); // band voltage table (volt_table_bytes)
 
   int band, tg;
   if constexpr (MODE == ROW_FUSED) {
@@ -372,7 +398,7 @@ __global__ __launch_bounds__(kThreads) void k_rows(RowArgs a) {
   for (int i = threadIdx.x; i < 2 * N; i += kThreads) tws[i] = a.tw[i];
   const int t_lo = a.t0 + tg * a.t_group;
   const int t_hi = min(a.t0 + a.nt, t_lo + a.t_group);
-  row_band<N, P, MODE, KJ>(a, band, t_lo, t_hi, grid, tws, [&](int c, int t, int p, int row, int q, float2 v) {
+  row_band<N, P, MODE, KJ>(a, band, t_lo, t_hi, grid, tws, vtab, [&](int c, int t, int p, int row, int q, float2 v) {
     constexpr int W = cols_ce(N);
     store_stream(a.io + (((int64_t)(c - a.c0) * a.t_block + (t - a.t0)) * P + p) * N * N +
                      (int64_t)(q / W) * (N * W) + row * W + (q % W),
@@ -707,7 +733,8 @@ __device__ __forceinline__ void stream_rows(const StreamArgs &s, int x, int r, i
     const int sl = (int)(u % S);
     if (u >= S) wg_wait(cons + sl, (uint32_t)(G * slot_count(u - S, sl, S)), s.err, s.spin_limit);
     float2 *dst = ring + sl * slot_elems;
-    row_band<N, P, ROW_FUSED, KJ>(s.r, bf + b, t0 + t, t0 + t + 1, work, tws,
+    char *vtab = reinterpret_cast<char *>(work + P * band_rows_ce(N, P) * row_stride(N));   // after the band grid
+    row_band<N, P, ROW_FUSED, KJ>(s.r, bf + b, t0 + t, t0 + t + 1, work, tws, vtab,
                                   [&](int, int, int p, int row, int q, float2 v) {
                                     store_coherent(dst + (int64_t)p * N * N + (q / W) * (N * W) + row * W + (q % W), v);
                                   });
@@ -831,11 +858,10 @@ __global__ void k_read_image(ReadArgs a) {
 // ------------------------------------------------------------------------------------------------------------
 // Launchers
 // ------------------------------------------------------------------------------------------------------------
-size_t rows_lds_bytes(int n, int P, int band_rows, int A, int volt_fmt) {
-  (void)A;
-  (void)volt_fmt;
+size_t rows_lds_bytes(int n, int P, int band_rows, int band_ants, int volt_fmt) {
   if (!fft_radix_max(n)) return 0;
-  return (size_t)P * band_rows * row_stride(n) * 8 + (size_t)2 * n * 8;
+  return (size_t)P * band_rows * row_stride(n) * 8 + (size_t)2 * n * 8 +
+         (row_stages_volts(n) ? volt_table_bytes(band_ants, P, volt_fmt) : 0);
 }
 
 size_t cols_lds_bytes(int n, int P, int W) {
@@ -1015,19 +1041,20 @@ static void *stream_kernel(int n, int P, int accm, bool jones) {
 #undef SCASE
 }
 
-size_t stream_lds_bytes(int n, int P) {
-  const size_t rows = (size_t)P * band_rows_ce(n, P) * row_stride(n) * 8;
+size_t stream_lds_bytes(int n, int P, int band_ants, int volt_fmt) {
+  const size_t rows = (size_t)P * band_rows_ce(n, P) * row_stride(n) * 8 +
+                      (row_stages_volts(n) ? volt_table_bytes(band_ants, P, volt_fmt) : 0);
   const size_t cols = cols_lds_bytes(n, P, cols_ce(n)) - (size_t)2 * n * 8;
   return (size_t)2 * n * 8 + (rows > cols ? rows : cols);
 }
 
-hipError_t stream_occupancy(int n, int P, int accm, bool jones, int *wgs_per_cu) {
+hipError_t stream_occupancy(int n, int P, int accm, bool jones, int band_ants, int volt_fmt, int *wgs_per_cu) {
   void *fn = stream_kernel(n, P, accm, jones);
   if (!fn) return hipErrorInvalidValue;
   hipError_t e = set_lds_limit_ext(fn);
   if (e != hipSuccess) return e;
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(wgs_per_cu, (const void *)fn, kThreads,
-                                                      stream_lds_bytes(n, P));
+                                                      stream_lds_bytes(n, P, band_ants, volt_fmt));
 }
 
 hipError_t launch_stream(int n, int P, int accm, bool jones, const StreamArgs &a, hipStream_t st) {
@@ -1035,8 +1062,8 @@ hipError_t launch_stream(int n, int P, int accm, bool jones, const StreamArgs &a
   if (!fn) return hipErrorInvalidValue;
   hipError_t e = set_lds_limit_ext(fn);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((void (*)(StreamArgs))fn, dim3(kXcds * a.wgs_per_xcd), dim3(kThreads), stream_lds_bytes(n, P),
-                     st, a);
+  hipLaunchKernelGGL((void (*)(StreamArgs))fn, dim3(kXcds * a.wgs_per_xcd), dim3(kThreads),
+                     stream_lds_bytes(n, P, a.r.band_ants_max, a.r.volt_fmt), st, a);
   return hipGetLastError();
 }
 

@@ -5,6 +5,7 @@
 
 #include <cstdint>
 
+#include "fft_sizes.h"
 #include "kernels.h"
 #include "mfma_fft.h"
 
@@ -17,6 +18,7 @@ constexpr int MHB = 8;             // rows per band (2 pols x 8 rows = 16 transf
 constexpr int MW = 8;              // columns per column-pass workgroup (2 pols x 8 columns = 16 transforms)
 constexpr int MTS = MN + 17;       // odd LDS stride per transform: the 16 lanes of a column hit 16 bank pairs
 static_assert(band_rows_ce(MN, MP) == MHB && cols_ce(MN) == MW, "launch geometry of the precision form");
+static_assert(row_stages_volts(MN), "the precision form reads voltages from the LDS table");
 }  // namespace
 
 // Matrix table (see mfma_fft.h), generated in FP64 from integer-reduced angles and split into 16-bit terms.
@@ -60,6 +62,7 @@ __global__ __launch_bounds__(kThreads) void k_rows_mfma(RowArgs a, const uint16_
   extern __shared__ float4 smem4[];
   float2 *grid = reinterpret_cast<float2 *>(smem4);        // [MP][MHB][MTS]
   float *ys = reinterpret_cast<float *>(grid + MP * MHB * MTS);
+  char *vtab = reinterpret_cast<char *>(ys + 2 * 16 * kYStride);   // band voltage table (volt_table_bytes)
 
   int band, tg;
   if (!rows_xcd_map(a, band, tg)) return;
@@ -76,14 +79,25 @@ __global__ __launch_bounds__(kThreads) void k_rows_mfma(RowArgs a, const uint16_
   constexpr int GCH = 8;
   MfmaMats<BF16> mats;
   mats.load(table, lane, wave);
+  // voltages staged in LDS per sample, as in the FP32 row pass: thread i copies the i-th antenna of the band
+  const int bcnt = bp->ant_cnt;
+  const int32_t *blist = a.band_ant + bp->ant_off;
+  const int my_ant = (int)threadIdx.x < bcnt ? blist[threadIdx.x] : -1;
+  auto vrow_of = [&](int t) {
+    return reinterpret_cast<const char *>(a.volt) + ((int64_t)t * a.n_chan + c) * vbytes;
+  };
+  uint4 nxt = make_uint4(0u, 0u, 0u, 0u);
+  if (my_ant >= 0 && t_lo < t_hi) nxt = fetch_volt_rec<MP>(vrow_of(t_lo), a.volt_fmt, my_ant);
 
   for (int t = t_lo; t < t_hi; ++t) {
+    if (my_ant >= 0) put_volt_rec<MP>(vtab, a.volt_fmt, threadIdx.x, nxt);
+    for (int i = threadIdx.x + kThreads; i < bcnt; i += kThreads)
+      put_volt_rec<MP>(vtab, a.volt_fmt, i, fetch_volt_rec<MP>(vrow_of(t), a.volt_fmt, blist[i]));
     {
       float4 *g4 = reinterpret_cast<float4 *>(grid);
       for (int i = threadIdx.x; i < MP * MHB * MTS / 2; i += kThreads) g4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
     __syncthreads();
-    const char *vrow = reinterpret_cast<const char *>(a.volt) + ((int64_t)t * a.n_chan + c) * vbytes;
     for (int g = 0; g < gc; g += GCH) {
       uint32_t m[GCH];
       float2 w[GCH][MP];
@@ -96,7 +110,7 @@ __global__ __launch_bounds__(kThreads) void k_rows_mfma(RowArgs a, const uint16_
           w[k][p] = ok ? a.wk[((g0 + g + k) * MP + p) * 64 + lane] : make_float2(0.f, 0.f);
       }
       float2 e[GCH][MP];
-      load_volts<MP, GCH>(vrow, a.volt_fmt, m, e);
+      load_volts<MP, GCH>(vtab, a.volt_fmt, m, e);
 #pragma unroll
       for (int k = 0; k < GCH; ++k) {
         if (m[k] != kEmptyTap) {
@@ -113,6 +127,7 @@ __global__ __launch_bounds__(kThreads) void k_rows_mfma(RowArgs a, const uint16_
       }
     }
     __syncthreads();
+    if (my_ant >= 0 && t + 1 < t_hi) nxt = fetch_volt_rec<MP>(vrow_of(t + 1), a.volt_fmt, my_ant);
     // 16 row transforms (pol p, band row r) = transform p * 8 + r; outputs back into the grid (its reads
     // finished at the barrier inside the FFT)
     fft256x16_mfma<BF16>(grid, MTS, ys, mats,
@@ -219,7 +234,9 @@ __global__ __launch_bounds__(kThreads) void k_cols_mfma(ColArgs a, const uint16_
     }
 }
 
-size_t rows_mfma_lds_bytes() { return (size_t)MP * MHB * MTS * 8 + (size_t)2 * 16 * kYStride * 4; }
+size_t rows_mfma_lds_bytes(int band_ants, int volt_fmt) {
+  return (size_t)MP * MHB * MTS * 8 + (size_t)2 * 16 * kYStride * 4 + volt_table_bytes(band_ants, MP, volt_fmt);
+}
 size_t cols_mfma_lds_bytes() { return (size_t)16 * MTS * 8 + (size_t)2 * 16 * kYStride * 4; }
 
 hipError_t launch_mfma_table(uint16_t *tab, int bf16, hipStream_t st) {
@@ -232,7 +249,7 @@ hipError_t launch_rows_mfma(int bf16, const RowArgs &a, const uint16_t *table, i
   void (*fn)(RowArgs, const uint16_t *) = bf16 ? k_rows_mfma<true> : k_rows_mfma<false>;
   hipError_t e = set_lds_limit_ext((const void *)fn);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(fn, dim3(grid), dim3(kThreads), rows_mfma_lds_bytes(), st, a, table);
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(kThreads), rows_mfma_lds_bytes(a.band_ants_max, a.volt_fmt), st, a, table);
   return hipGetLastError();
 }
 

@@ -68,6 +68,8 @@ moff::RowArgs row_args(const moff::Plan &p, const void *volt) {
   a.volt = volt;
   a.volt_fmt = p.volt_format;
   a.meta = reinterpret_cast<const uint32_t *>(ws(p, p.ws_meta));
+  a.band_ant = reinterpret_cast<const int32_t *>(ws(p, p.ws_band_ant));
+  a.band_ants_max = p.max_band_ants;
   a.wk = reinterpret_cast<const float2 *>(ws(p, p.ws_wk));
   a.t_group = p.t_group;
   a.t_block = p.t_block;
@@ -155,7 +157,8 @@ moff_status enqueue_stream(moff::Plan &p, const void *d_volt, int64_t n_t, void 
     int c1 = c0;
     while (c1 < p.n_chan && p.chans[c1].n == n) ++c1;
     int occ = 0;
-    HIP_TRY(moff::stream_occupancy(n, p.n_pol, p.acc_mode, jones, &occ), "stream occupancy");
+    HIP_TRY(moff::stream_occupancy(n, p.n_pol, p.acc_mode, jones, p.max_band_ants, p.volt_format, &occ),
+            "stream occupancy");
     const int per_xcd = occ * (p.cu_count / moff::kStreamXcds);
     const int owners = n / p.chans[c0].cols;
     if (per_xcd < owners + owners / 2) {
@@ -222,7 +225,7 @@ moff_status enqueue_two_pass(moff::Plan &p, const void *d_volt, int64_t n_t, voi
       a.nt = nt;
       a.tw = d_tw(p, b.n);
       const int tgroups = (nt + p.t_group - 1) / p.t_group;
-      const size_t lds = moff::rows_lds_bytes(b.n, p.n_pol, p.chans[b.c0].band_rows, p.n_ant, p.volt_format);
+      const size_t lds = moff::rows_lds_bytes(b.n, p.n_pol, p.chans[b.c0].band_rows, p.max_band_ants, p.volt_format);
       const int64_t cs = (int64_t)nt * (b.c1 - b.c0);
       const bool split = p.fft_mode != MOFF_FFT_FP32;
       const int bf16 = p.fft_mode == MOFF_FFT_SPLIT_BF16;
@@ -326,7 +329,7 @@ moff_status moff_plan(const moff_plan_desc *desc, moff_plan_t *out) {
   }
   const moff::Plan &p = h->p;
   for (const moff::Chan &c : p.chans) {
-    if (moff::rows_lds_bytes(c.n, p.n_pol, c.band_rows, p.n_ant, p.volt_format) > (size_t)moff::kMaxLds ||
+    if (moff::rows_lds_bytes(c.n, p.n_pol, c.band_rows, p.max_band_ants, p.volt_format) > (size_t)moff::kMaxLds ||
         moff::cols_lds_bytes(c.n, p.n_pol, c.cols) > (size_t)moff::kMaxLds) {
       delete h;
       return set_err(MOFF_E_UNSUPPORTED, "grid size needs more LDS than a CU has");
@@ -404,6 +407,10 @@ moff_status moff_bind(moff_plan_t plan, void *d_ws, size_t bytes, void *stream) 
     HIP_TRY(hipMemcpyAsync(ws(p, p.ws_gchan), p.grp_chan.data(), p.grp_chan.size() * 4, hipMemcpyHostToDevice, st),
             "upload group channels");
   }
+  if (!p.band_ant.empty())
+    HIP_TRY(hipMemcpyAsync(ws(p, p.ws_band_ant), p.band_ant.data(), p.band_ant.size() * 4, hipMemcpyHostToDevice,
+                           st),
+            "upload band antenna lists");
   for (size_t i = 0; i < p.tw_sizes.size(); ++i)
     HIP_TRY(moff::launch_twiddle(reinterpret_cast<float2 *>(ws(p, p.tw_off[i])), p.tw_sizes[i], st), "twiddles");
   if (p.fft_mode != MOFF_FFT_FP32)
@@ -462,7 +469,7 @@ moff_status moff_grid(moff_plan_t plan, const void *d_volt, int64_t n_t, void *d
     a.c0 = b.c0;
     a.tw = d_tw(p, b.n);
     const int tgroups = (int)((n_t + p.t_group - 1) / p.t_group);
-    const size_t lds = moff::rows_lds_bytes(b.n, p.n_pol, p.chans[b.c0].band_rows, p.n_ant, p.volt_format);
+    const size_t lds = moff::rows_lds_bytes(b.n, p.n_pol, p.chans[b.c0].band_rows, p.max_band_ants, p.volt_format);
     HIP_TRY(moff::launch_rows(b.n, p.n_pol, moff::ROW_MODE_GRID, jones, a, a.n_bands * tgroups, lds, st), "grid");
   }
   return ok();
@@ -496,7 +503,7 @@ moff_status moff_fft(moff_plan_t plan, void *d_grid, int64_t n_t, void *stream) 
     a.c0 = b.c0;
     a.tw = d_tw(p, b.n);
     const int tgroups = (int)((n_t + p.t_group - 1) / p.t_group);
-    const size_t lds = moff::rows_lds_bytes(b.n, p.n_pol, p.chans[b.c0].band_rows, p.n_ant, p.volt_format);
+    const size_t lds = moff::rows_lds_bytes(b.n, p.n_pol, p.chans[b.c0].band_rows, p.max_band_ants, p.volt_format);
     HIP_TRY(moff::launch_rows(b.n, p.n_pol, moff::ROW_MODE_FFT, false, a, a.n_bands * tgroups, lds, st), "row fft");
   }
   for (const moff::Block &b : p.blocks) {

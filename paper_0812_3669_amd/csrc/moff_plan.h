@@ -29,6 +29,7 @@ struct Band {
   int32_t r_lo, r_hi;   // rows [r_lo, r_hi] of the band that any footprint touches (absolute)
   int64_t grp_off[kWaves];  // first tap group of each wavefront (index into the group arrays)
   int32_t grp_cnt[kWaves];
+  int32_t ant_off, ant_cnt; // the band's antennas: band_ant[ant_off .. ant_off + ant_cnt), ascending
 };
 
 struct Chan {
@@ -61,7 +62,10 @@ struct Plan {
   std::vector<Band> bands;
   std::vector<int32_t> band_ptr;        // [n_bands + 1] into band_ant
   std::vector<int32_t> band_ant;        // antennas of each band, ascending
-  // tap groups: meta = (antenna << 16) | cell offset in the band grid ((r - row0) * n + i); kidx = a*K*K + y*K + x
+  int32_t max_band_ants = 0;           // largest band antenna list of the sizes with a voltage table (LDS size)
+  // tap groups: meta = (antenna << 16) | cell offset in the band grid ((r - row0) * n + i), where the antenna is
+  // its position in the band's list for sizes whose row pass stages voltages (row_stages_volts) and its index
+  // otherwise; kidx = a*K*K + y*K + x
   std::vector<uint32_t> grp_meta;       // [G][64]
   std::vector<int32_t> grp_kidx;        // [G][64]
   std::vector<int32_t> grp_chan;        // [G] channel of each group
@@ -87,6 +91,7 @@ struct Plan {
   size_t ws_bands = 0;                  // Band array (device copy)
   size_t ws_chans = 0;                  // Chan array (device copy)
   size_t ws_meta = 0, ws_kidx = 0, ws_gchan = 0, ws_wk = 0;  // tap groups; packed kernels float2 [G][P][64]
+  size_t ws_band_ant = 0;               // band antenna lists (int32)
   size_t ws_mfma = 0;                   // split-transform matrices (split fft modes only)
   size_t ws_ring = 0, ws_ctr = 0;       // streaming form: per-XCD ring of row-transformed samples; counters
   size_t ws_tap_tw = 0, ws_tap_twoff = 0, ws_tap_idx = 0, ws_tap_cpix = 0, ws_origin = 0;   // taps

@@ -171,6 +171,7 @@ moff_status build_plan(const moff_plan_desc &d, Plan &p, std::string *err) {
 
   // ---- row bands, band antenna lists and tap groups ------------------------------------------------------
   p.bands.clear();
+  p.max_band_ants = 0;
   p.band_ptr.assign(1, 0);
   p.band_ant.clear();
   p.grp_meta.clear();
@@ -196,6 +197,9 @@ moff_status build_plan(const moff_plan_desc &d, Plan &p, std::string *err) {
       }
       const int32_t lo = p.band_ptr.back(), hi = (int32_t)p.band_ant.size();
       p.band_ptr.push_back(hi);
+      bd.ant_off = lo;
+      bd.ant_cnt = hi - lo;
+      if (row_stages_volts(n)) p.max_band_ants = std::max(p.max_band_ants, hi - lo);
       // tap groups per wavefront: 64 taps on 64 distinct cells per group, antennas ascending, first fit, so every
       // cell receives its contributions in ascending antenna order (deterministic sums, no atomics).  Lane
       // 16 q + k of a group holds a tap whose LDS word offset is k mod 16, so the 16 lanes a quarter-wave
@@ -234,7 +238,7 @@ moff_status build_plan(const moff_plan_desc &d, Plan &p, std::string *err) {
                 if (lane >= 0) break;
               }
               const size_t slot = (size_t)(g0 + g) * kGroupLanes + lane;
-              p.grp_meta[slot] = ((uint32_t)a << 16) | (uint32_t)cell;
+              p.grp_meta[slot] = ((uint32_t)(row_stages_volts(n) ? e - lo : a) << 16) | (uint32_t)cell;
               p.grp_kidx[slot] = (a * K + y) * K + x;
               used[g] |= (uint64_t)1 << lane;
               ++count[g];
@@ -277,6 +281,8 @@ moff_status build_plan(const moff_plan_desc &d, Plan &p, std::string *err) {
   off = align256(off + p.grp_chan.size() * 4);
   p.ws_wk = off;
   off = align256(off + (size_t)p.n_groups * p.kplanes() * kGroupLanes * 8);
+  p.ws_band_ant = off;
+  off = align256(off + p.band_ant.size() * 4);
   p.ws_mfma = off;
   if (p.fft_mode != MOFF_FFT_FP32) off = align256(off + kMfmaTableBytesHost);
   // streaming form: kStreamXcds rings of stream_slots row-transformed samples of the largest grid, then the
