@@ -58,7 +58,7 @@ __global__ void k_mfma_table(uint16_t *tab, int bf16) {
 }
 
 template <bool BF16>
-__global__ __launch_bounds__(kThreads) void k_rows_mfma(RowArgs a, const uint16_t *table) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_rows_mfma(RowArgs a, const uint16_t *table) {
   extern __shared__ float4 smem4[];
   float2 *grid = reinterpret_cast<float2 *>(smem4);        // [MP][MHB][MTS]
   float *ys = reinterpret_cast<float *>(grid + MP * MHB * MTS);
@@ -86,11 +86,17 @@ __global__ __launch_bounds__(kThreads) void k_rows_mfma(RowArgs a, const uint16_
   auto vrow_of = [&](int t) {
     return reinterpret_cast<const char *>(a.volt) + ((int64_t)t * a.n_chan + c) * vbytes;
   };
-  uint4 nxt = make_uint4(0u, 0u, 0u, 0u);
-  if (my_ant >= 0 && t_lo < t_hi) nxt = fetch_volt_rec<MP>(vrow_of(t_lo), a.volt_fmt, my_ant);
+  // int8 records (one register) are loaded one sample ahead; float records are copied when they are staged
+  const bool pre8 = a.volt_fmt == 0 && my_ant >= 0;
+  uint32_t nxt = 0u;
+  if (pre8 && t_lo < t_hi) nxt = fetch_volt_rec<MP>(vrow_of(t_lo), 0, my_ant).x;
 
   for (int t = t_lo; t < t_hi; ++t) {
-    if (my_ant >= 0) put_volt_rec<MP>(vtab, a.volt_fmt, threadIdx.x, nxt);
+    if (pre8) {
+      if (t == t_lo) put_volt_rec<MP>(vtab, 0, threadIdx.x, make_uint4(nxt, 0u, 0u, 0u));
+    } else if (my_ant >= 0) {
+      put_volt_rec<MP>(vtab, a.volt_fmt, threadIdx.x, fetch_volt_rec<MP>(vrow_of(t), a.volt_fmt, my_ant));
+    }
     for (int i = threadIdx.x + kThreads; i < bcnt; i += kThreads)
       put_volt_rec<MP>(vtab, a.volt_fmt, i, fetch_volt_rec<MP>(vrow_of(t), a.volt_fmt, blist[i]));
     {
@@ -127,11 +133,14 @@ __global__ __launch_bounds__(kThreads) void k_rows_mfma(RowArgs a, const uint16_
       }
     }
     __syncthreads();
-    if (my_ant >= 0 && t + 1 < t_hi) nxt = fetch_volt_rec<MP>(vrow_of(t + 1), a.volt_fmt, my_ant);
+    if (pre8 && t + 1 < t_hi) nxt = fetch_volt_rec<MP>(vrow_of(t + 1), 0, my_ant).x;
     // 16 row transforms (pol p, band row r) = transform p * 8 + r; outputs back into the grid (its reads
     // finished at the barrier inside the FFT)
     fft256x16_mfma<BF16>(grid, MTS, ys, mats,
                          [&](int tt, int q, float2 v, int, int) { grid[tt * MTS + q] = v; });
+    // the next sample's records go to the table (this sample's scatter is over) before the stores are issued, so
+    // the wait for their loads does not also wait for the stores
+    if (pre8 && t + 1 < t_hi) put_volt_rec<MP>(vtab, 0, threadIdx.x, make_uint4(nxt, 0u, 0u, 0u));
     __syncthreads();
     // touched rows to the column-group tiles of H: [p][q / W][row][q % W], 8 rows x 8 columns contiguous
     float2 *hb = a.io + ((int64_t)(c - a.c0) * a.t_block + (t - a.t0)) * MP * MN * MN;
