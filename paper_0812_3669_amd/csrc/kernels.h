@@ -130,27 +130,23 @@ struct StreamArgs {
   uint32_t spin_limit;
 };
 
-// Voltages of G taps at once from a voltage row laid out like the caller's (record = meta >> 16; empty taps give
-// 0): the row pass reads its band's LDS voltage table this way.  The format branch is uniform and outside the
-// unrolled reads, and the reads are unconditional (an empty tap reads record 0), so all G are issued before the
-// first is used.
+// Voltages of G taps at once from a voltage row laid out like the caller's (record = meta >> 16): the row pass
+// reads its band's LDS voltage table, or the voltage row itself, this way.  The format branch is uniform and
+// outside the unrolled reads, and the reads are unconditional, so all G are issued before the first is used.
 template <int P, int G>
 __device__ __forceinline__ void load_volts(const void *row, int fmt, const uint32_t (&m)[G], float2 (&e)[G][P]) {
-  int ant[G];
-#pragma unroll
-  for (int k = 0; k < G; ++k) ant[k] = m[k] != kEmptyTap ? (int)(m[k] >> 16) : 0;
   if (fmt == 0) {
     uint32_t w[G];
 #pragma unroll
     for (int k = 0; k < G; ++k) {
       if constexpr (P == 2)
-        w[k] = reinterpret_cast<const uint32_t *>(row)[ant[k]];
+        w[k] = reinterpret_cast<const uint32_t *>(row)[m[k] >> 16];
       else
-        w[k] = reinterpret_cast<const uint16_t *>(row)[ant[k]];
+        w[k] = reinterpret_cast<const uint16_t *>(row)[m[k] >> 16];
     }
 #pragma unroll
     for (int k = 0; k < G; ++k) {
-      const uint32_t v = m[k] != kEmptyTap ? w[k] : 0u;
+      const uint32_t v = w[k];
       e[k][0] = make_float2((float)(int8_t)(v & 0xFF), (float)(int8_t)((v >> 8) & 0xFF));
       if constexpr (P == 2) e[k][1] = make_float2((float)(int8_t)((v >> 16) & 0xFF), (float)(int8_t)(v >> 24));
     }
@@ -158,19 +154,15 @@ __device__ __forceinline__ void load_volts(const void *row, int fmt, const uint3
     if constexpr (P == 2) {
       float4 w[G];
 #pragma unroll
-      for (int k = 0; k < G; ++k) w[k] = reinterpret_cast<const float4 *>(row)[ant[k]];
+      for (int k = 0; k < G; ++k) w[k] = reinterpret_cast<const float4 *>(row)[m[k] >> 16];
 #pragma unroll
       for (int k = 0; k < G; ++k) {
-        const bool ok = m[k] != kEmptyTap;
-        e[k][0] = ok ? make_float2(w[k].x, w[k].y) : make_float2(0.f, 0.f);
-        e[k][1] = ok ? make_float2(w[k].z, w[k].w) : make_float2(0.f, 0.f);
+        e[k][0] = make_float2(w[k].x, w[k].y);
+        e[k][1] = make_float2(w[k].z, w[k].w);
       }
     } else {
-      float2 w[G];
 #pragma unroll
-      for (int k = 0; k < G; ++k) w[k] = reinterpret_cast<const float2 *>(row)[ant[k]];
-#pragma unroll
-      for (int k = 0; k < G; ++k) e[k][0] = m[k] != kEmptyTap ? w[k] : make_float2(0.f, 0.f);
+      for (int k = 0; k < G; ++k) e[k][0] = reinterpret_cast<const float2 *>(row)[m[k] >> 16];
     }
   }
 }

@@ -244,13 +244,13 @@ __device__ __forceinline__ void row_band(const RowArgs &a, int band, int t_lo, i
     return (p * HB + (bd.r_lo - bd.row0 + r)) * TS;
   };
 
-  // one tap: grid cell m gets w * e (pol by pol; Jones: both pols into each grid)
+  // one tap: grid cell m gets w * e (pol by pol; Jones: both pols into each grid); the cell is the element offset
+  // in a pol's band grid (row * TS + column)
   auto scatter_tap = [&](uint32_t m, const float2 (&w)[PL], const float2 (&e)[P]) {
     const int cell = (int)(m & 0xFFFFu);
-    const int rr = cell / N, col = cell - rr * N;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-      float2 *cellp = grid + (p * HB + rr) * TS + col;
+      float2 *cellp = grid + p * HB * TS + cell;
       float2 cur = *cellp;
       if constexpr (KJ) {
         // grid p receives both pols: K_{p0} E_0 + K_{p1} E_1
@@ -308,14 +308,14 @@ __device__ __forceinline__ void row_band(const RowArgs &a, int band, int t_lo, i
           float2 w[GCH][PL];
 #pragma unroll
           for (int k = 0; k < GCH; ++k) {
-            const bool ok = g + k < gc;
-            m[k] = ok ? a.meta[(g0 + g + k) * 64 + lane] : kEmptyTap;
+            const bool ok = g + k < gc;   // uniform: groups past the wave's last are not scattered
+            m[k] = ok ? a.meta[(g0 + g + k) * 64 + lane] : 0u;
 #pragma unroll
             for (int p = 0; p < PL; ++p)
               w[k][p] = ok ? a.wk[((g0 + g + k) * PL + p) * 64 + lane] : make_float2(0.f, 0.f);
           }
-          // voltages of the GCH groups' taps from the LDS table or the voltage row (an empty lane reads record 0
-          // and discards it; the loads are branch-free, so all GCH are in flight together)
+          // voltages of the GCH groups' taps from the LDS table or the voltage row (the loads are branch-free, so
+          // all GCH are in flight together; an empty lane reads antenna 0 and adds it with zero weights)
           float2 e[GCH][P];
           if constexpr (STAGE)
             load_volts<P, GCH>(vtab, a.volt_fmt, m, e);
@@ -323,7 +323,7 @@ __device__ __forceinline__ void row_band(const RowArgs &a, int band, int t_lo, i
             load_volts<P, GCH>(vrow_of(t), a.volt_fmt, m, e);
 #pragma unroll
           for (int k = 0; k < GCH; ++k)
-            if (m[k] != kEmptyTap) scatter_tap(m[k], w[k], e[k]);
+            if (g + k < gc) scatter_tap(m[k], w[k], e[k]);
         }
       }
       __syncthreads();

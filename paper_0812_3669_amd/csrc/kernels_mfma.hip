@@ -110,7 +110,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
 #pragma unroll
       for (int k = 0; k < GCH; ++k) {
         const bool ok = g + k < gc;
-        m[k] = ok ? a.meta[(g0 + g + k) * 64 + lane] : kEmptyTap;
+        m[k] = ok ? a.meta[(g0 + g + k) * 64 + lane] : 0u;
 #pragma unroll
         for (int p = 0; p < MP; ++p)
           w[k][p] = ok ? a.wk[((g0 + g + k) * MP + p) * 64 + lane] : make_float2(0.f, 0.f);
@@ -119,9 +119,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
       load_volts<MP, GCH>(vtab, a.volt_fmt, m, e);
 #pragma unroll
       for (int k = 0; k < GCH; ++k) {
-        if (m[k] != kEmptyTap) {
+        if (g + k < gc) {
+          // the cell is an element offset in the FP32 band layout (row stride row_stride(256))
           const int cell = (int)(m[k] & 0xFFFFu);
-          const int rr = cell / MN, col = cell - rr * MN;
+          const int rr = cell / row_stride(MN), col = cell - rr * row_stride(MN);
 #pragma unroll
           for (int p = 0; p < MP; ++p) {
             float2 *cp = grid + (p * MHB + rr) * MTS + col;

@@ -63,9 +63,10 @@ struct Plan {
   std::vector<int32_t> band_ptr;        // [n_bands + 1] into band_ant
   std::vector<int32_t> band_ant;        // antennas of each band, ascending
   int32_t max_band_ants = 0;           // largest band antenna list of the sizes with a voltage table (LDS size)
-  // tap groups: meta = (antenna << 16) | cell offset in the band grid ((r - row0) * n + i), where the antenna is
-  // its position in the band's list for sizes whose row pass stages voltages (row_stages_volts) and its index
-  // otherwise; kidx = a*K*K + y*K + x
+  // tap groups: meta = (antenna << 16) | cell, the cell being the element offset in a pol's band grid in LDS
+  // ((r - row0) * row_stride(n) + i) and the antenna its position in the band's list for sizes whose row pass
+  // stages voltages (row_stages_volts), its index otherwise; kidx = a*K*K + y*K + x.  Empty lanes hold antenna 0
+  // and a cell no other lane of the group uses, with kidx -1 (zero weights).
   std::vector<uint32_t> grp_meta;       // [G][64]
   std::vector<int32_t> grp_kidx;        // [G][64]
   std::vector<int32_t> grp_chan;        // [G] channel of each group

@@ -207,7 +207,7 @@ moff_status build_plan(const moff_plan_desc &d, Plan &p, std::string *err) {
       const int ts = row_stride(n);
       for (int w = 0; w < kWaves; ++w) {
         const int64_t g0 = p.n_groups;
-        last_used.assign((size_t)bd.rows * n, -1);
+        last_used.assign((size_t)bd.rows * ts, -1);
         std::vector<uint64_t> used;      // per group: bit 16 q + k set when lane 16 q + k is taken
         std::vector<int32_t> count;
         int64_t first_open = 0;
@@ -218,8 +218,8 @@ moff_status build_plan(const moff_plan_desc &d, Plan &p, std::string *err) {
             const int r = j0 + y - bd.row0;
             if (r < 0 || r >= bd.rows || (r % kWaves) != w) continue;
             for (int x = 0; x < K; ++x) {
-              const int cell = r * n + i0 + x;
-              const int key = (r * ts + i0 + x) & 15;
+              const int cell = r * ts + i0 + x;   // element offset in a pol's band grid in LDS
+              const int key = cell & 15;
               int64_t g = std::max<int64_t>(first_open, (int64_t)last_used[cell] + 1);
               int lane = -1;
               for (;; ++g) {
@@ -245,6 +245,28 @@ moff_status build_plan(const moff_plan_desc &d, Plan &p, std::string *err) {
               last_used[cell] = (int32_t)g;
               while (first_open < (int64_t)count.size() && count[first_open] == kGroupLanes) ++first_open;
             }
+          }
+        }
+        // empty lanes get a cell in one of this wavefront's rows (other wavefronts scatter into theirs at the same
+        // time) that no other lane of their group uses (same bank key), and zero weights (kidx -1): they add 0
+        // there, so the row pass needs no per-lane emptiness test
+        for (size_t g = 0; g < count.size(); ++g) {
+          uint32_t *gm = p.grp_meta.data() + (size_t)(g0 + (int64_t)g) * kGroupLanes;
+          int taken[16][kGroupLanes / 16], n_taken[16] = {};   // cells in use per bank key (4 lanes per key)
+          for (int l = 0; l < kGroupLanes; ++l)
+            if (gm[l] != kEmptyTap) taken[l & 15][n_taken[l & 15]++] = (int)(gm[l] & 0xFFFFu);
+          for (int l = 0; l < kGroupLanes; ++l) {
+            if (gm[l] != kEmptyTap) continue;
+            const int key = l & 15;
+            int cell = key;
+            for (bool used = true; used && cell < bd.rows * ts;) {
+              used = (cell / ts) % kWaves != w;
+              for (int u = 0; u < n_taken[key]; ++u) used |= taken[key][u] == cell;
+              if (used) cell += 16;
+            }
+            if (cell >= bd.rows * ts) return fail(err, MOFF_E_INVALID, "no free cell for an empty tap lane");
+            taken[key][n_taken[key]++] = cell;
+            gm[l] = (uint32_t)cell;
           }
         }
         bd.grp_off[w] = g0;

@@ -1,5 +1,6 @@
 // Host-only driver of the plan builder (plan.cpp) for the sanitizer test: builds plans for several layouts
 // (fixed and automatic grid sizes, taps, a single antenna, a footprint leaving the grid) with no HIP code.
+#include "fft_sizes.h"
 #include "moff_plan.h"
 #include <cstdio>
 #include <cmath>
@@ -19,7 +20,23 @@ int run(int A, int C, int n, int K, double disk, int P, int ntap, int seed) {
   int s = moff::build_plan(d, p, &err);
   if (s) { printf("A=%d C=%d n=%d K=%d: status %d (%s)\n", A, C, n, K, s, err.c_str()); return s; }
   long taps = 0;
-  for (auto m : p.grp_meta) taps += (m != moff::kEmptyTap);
+  for (auto k : p.grp_kidx) taps += (k >= 0);
+  for (auto m : p.grp_meta) if (m == moff::kEmptyTap) { printf("unfilled lane\n"); return 1; }
+  // every lane of a wavefront's groups (empty ones included) scatters into that wavefront's rows only, and the
+  // cells of one group are distinct
+  for (auto &b : p.bands) {
+    const int ts = moff::row_stride(p.chans[b.chan].n);
+    for (int w = 0; w < moff::kWaves; ++w)
+      for (int g = 0; g < b.grp_cnt[w]; ++g) {
+        const uint32_t *gm = p.grp_meta.data() + (b.grp_off[w] + g) * moff::kGroupLanes;
+        for (int l = 0; l < moff::kGroupLanes; ++l) {
+          const int cell = (int)(gm[l] & 0xFFFFu);
+          if ((cell / ts) % moff::kWaves != w || cell >= b.rows * ts) { printf("lane outside its rows\n"); return 1; }
+          for (int k = 0; k < l; ++k)
+            if ((int)(gm[k] & 0xFFFFu) == cell) { printf("two lanes on one cell\n"); return 1; }
+        }
+      }
+  }
   printf("A=%d C=%d n=%d K=%d P=%d: bands %zu groups %lld taps %ld ws %zu\n", A, C, n, K, P, p.bands.size(), (long long)p.n_groups, taps, p.ws_total);
   for (int tb : {1, 8, 64}) for (int cpb : {1, 7, 64}) moff::layout_blocks(p, tb, cpb, 4);
   return 0;
