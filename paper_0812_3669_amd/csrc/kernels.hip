@@ -270,9 +270,8 @@ __device__ __forceinline__ void row_band(const RowArgs &a, int band, int t_lo, i
   // voltages: thread i copies the record of the i-th antenna of the band's list (ascending) into the LDS table
   // vtab before each sample's scatter, so the scatter reads its voltages from LDS (coalesced global loads instead
   // of per-tap gathers).  int8 records (one register) are loaded for the next sample right after this sample's
-  // scatter and, in the fused pass, written to the table before this sample's H stores are issued, so the wait
-  // for the load does not also wait for the stores (vector memory operations complete in order); float records
-  // are copied when they are staged.
+  // scatter and written to the table after the next sample's clear; float records are copied when they are
+  // staged.
   constexpr bool SCAT = MODE == ROW_FUSED || MODE == ROW_GRID;
   constexpr bool STAGE = SCAT && row_stages_volts(N);
   const int bcnt = STAGE ? bp->ant_cnt : 0;
@@ -287,18 +286,26 @@ __device__ __forceinline__ void row_band(const RowArgs &a, int band, int t_lo, i
 
   for (int t = t_lo; t < t_hi; ++t) {
     if constexpr (SCAT) {
-      if (pre8) {
-        if (MODE != ROW_FUSED || t == t_lo) put_volt_rec<P>(vtab, 0, threadIdx.x, make_uint4(nxt, 0u, 0u, 0u));
-      } else if (my_ant >= 0)
+      // clear the band grid (16-byte stores over the whole contiguous region, unrolled: no loop between the
+      // previous sample's stores and the record write below)
+      {
+        float4 *g4 = reinterpret_cast<float4 *>(grid);
+        constexpr int NCLR = P * HB * TS / 2;
+#pragma unroll
+        for (int k = 0; k < (NCLR + kThreads - 1) / kThreads; ++k) {
+          const int i = threadIdx.x + k * kThreads;
+          if (NCLR % kThreads == 0 || i < NCLR) g4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+      }
+      // the int8 record loaded after the previous sample's scatter: waiting for it also waits for the previous
+      // sample's stores (vector memory operations complete in order), as the scatter's loads below would, so the
+      // wait comes after the clear
+      if (pre8)
+        put_volt_rec<P>(vtab, 0, threadIdx.x, make_uint4(nxt, 0u, 0u, 0u));
+      else if (my_ant >= 0)
         put_volt_rec<P>(vtab, a.volt_fmt, threadIdx.x, fetch_volt_rec<P>(vrow_of(t), a.volt_fmt, my_ant));
       for (int i = threadIdx.x + kThreads; i < bcnt; i += kThreads)
         put_volt_rec<P>(vtab, a.volt_fmt, i, fetch_volt_rec<P>(vrow_of(t), a.volt_fmt, blist[i]));
-      // clear the band grid (16-byte stores over the whole contiguous region)
-      {
-        float4 *g4 = reinterpret_cast<float4 *>(grid);
-#pragma unroll 4
-        for (int i = threadIdx.x; i < P * HB * TS / 2; i += kThreads) g4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-      }
       __syncthreads();
       // deterministic scatter: this wavefront's tap groups, one tap per lane, 64 distinct cells per group;
       // the loads of GCH groups are issued before any of them is used
@@ -362,22 +369,15 @@ __device__ __forceinline__ void row_band(const RowArgs &a, int band, int t_lo, i
                (int64_t)row * N + q] = v;
         }
       };
-      // the next sample's int8 voltage records go to the table (its scatter is over) before the stores
-      auto put_next = [&]() {
-        if constexpr (MODE == ROW_FUSED)
-          if (pre8 && t + 1 < t_hi) put_volt_rec<P>(vtab, 0, threadIdx.x, make_uint4(nxt, 0u, 0u, 0u));
-      };
       if constexpr (PP::S == 2) {
         constexpr int MB1 = (P * HB * (N / PP::R1) + kThreads - 1) / kThreads;
         row_stage_lds<N, PP::R0, 1, 0, 1, MB0>(grid, ntr, tws, tr_base);
-        put_next();
         row_stage_out<N, PP::R1, PP::L1, PP::R0, 1, MB1>(grid, ntr, tws, tr_base, dst);
       } else {
         constexpr int MB1 = (P * HB * (N / PP::R1) + kThreads - 1) / kThreads;
         constexpr int MB2 = (P * HB * (N / PP::R2) + kThreads - 1) / kThreads;
         row_stage_lds<N, PP::R0, 1, 0, 1, MB0>(grid, ntr, tws, tr_base);
         row_stage_lds<N, PP::R1, PP::L1, PP::R0, 1, MB1>(grid, ntr, tws, tr_base);
-        put_next();
         row_stage_out<N, PP::R2, PP::L2, PP::R1, PP::L1, MB2>(grid, ntr, tws, tr_base, dst);
       }
       __syncthreads();
