@@ -167,6 +167,21 @@ __device__ __forceinline__ void load_volts(const void *row, int fmt, const uint3
   }
 }
 
+// One lane's packed kernel values of one tap group (planes contiguous, wk[g][lane][plane]): 16-byte loads.
+template <int PL>
+__device__ __forceinline__ void load_taps(const float2 *p, float2 (&w)[PL]) {
+  if constexpr (PL == 1) {
+    w[0] = p[0];
+  } else {
+#pragma unroll
+    for (int q = 0; q < PL / 2; ++q) {
+      const float4 v = reinterpret_cast<const float4 *>(p)[q];
+      w[2 * q] = make_float2(v.x, v.y);
+      w[2 * q + 1] = make_float2(v.z, v.w);
+    }
+  }
+}
+
 // Bytes of one antenna's voltages for one (sample, channel): P pols of (re, im), int8 (format 0) or float.
 __host__ __device__ constexpr int volt_rec_bytes(int P, int fmt) { return P * (fmt == 0 ? 2 : 8); }
 

@@ -58,7 +58,8 @@ __global__ void k_twiddle_f64(float2 *tw, int n, int r0, int r1, int r2) {
   tw[e] = make_float2((float)c, (float)s);
 }
 
-// Packs the caller's kernels into tap-group order wk[g][plane][lane]: diagonal kernels [C][A][P][K*K] give P
+// Packs the caller's kernels into tap-group order wk[g][lane][plane] (a lane's planes are contiguous: one 16-byte
+// load for two planes): diagonal kernels [C][A][P][K*K] give P
 // planes, Jones kernels [C][A][2][2][K*K] give planes 2 p + q.  Each is multiplied by the phase-centre phase of
 // the voltage it multiplies, phase[c][a][q], when one is given (W (phi E) = (W phi) E).
 __global__ void k_pack_kernels(const float2 *__restrict__ kern, const float2 *__restrict__ phase,
@@ -78,7 +79,7 @@ __global__ void k_pack_kernels(const float2 *__restrict__ kern, const float2 *__
       v = kern[(((int64_t)c * A + a) * planes + pl) * KK + tap];
       if (phase) v = cmul(v, phase[((int64_t)c * A + a) * P + q]);
     }
-    wk[(g * planes + pl) * 64 + lane] = v;
+    wk[(g * 64 + lane) * planes + pl] = v;
   }
 }
 
@@ -319,7 +320,8 @@ __device__ __forceinline__ void row_band(const RowArgs &a, int band, int t_lo, i
             m[k] = ok ? a.meta[(g0 + g + k) * 64 + lane] : 0u;
 #pragma unroll
             for (int p = 0; p < PL; ++p)
-              w[k][p] = ok ? a.wk[((g0 + g + k) * PL + p) * 64 + lane] : make_float2(0.f, 0.f);
+              w[k][p] = make_float2(0.f, 0.f);
+            if (ok) load_taps<PL>(a.wk + ((g0 + g + k) * 64 + lane) * PL, w[k]);
           }
           // voltages of the GCH groups' taps from the LDS table or the voltage row (the loads are branch-free, so
           // all GCH are in flight together; an empty lane reads antenna 0 and adds it with zero weights)

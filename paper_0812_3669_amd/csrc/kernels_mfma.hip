@@ -112,8 +112,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
         const bool ok = g + k < gc;
         m[k] = ok ? a.meta[(g0 + g + k) * 64 + lane] : 0u;
 #pragma unroll
-        for (int p = 0; p < MP; ++p)
-          w[k][p] = ok ? a.wk[((g0 + g + k) * MP + p) * 64 + lane] : make_float2(0.f, 0.f);
+        for (int p = 0; p < MP; ++p) w[k][p] = make_float2(0.f, 0.f);
+        if (ok) load_taps<MP>(a.wk + ((g0 + g + k) * 64 + lane) * MP, w[k]);
       }
       float2 e[GCH][MP];
       load_volts<MP, GCH>(vtab, a.volt_fmt, m, e);

@@ -91,7 +91,7 @@ struct Plan {
   std::vector<size_t> tw_off;           // byte offset of each table
   size_t ws_bands = 0;                  // Band array (device copy)
   size_t ws_chans = 0;                  // Chan array (device copy)
-  size_t ws_meta = 0, ws_kidx = 0, ws_gchan = 0, ws_wk = 0;  // tap groups; packed kernels float2 [G][P][64]
+  size_t ws_meta = 0, ws_kidx = 0, ws_gchan = 0, ws_wk = 0;  // tap groups; packed kernels float2 [G][64][planes]
   size_t ws_band_ant = 0;               // band antenna lists (int32)
   size_t ws_mfma = 0;                   // split-transform matrices (split fft modes only)
   size_t ws_ring = 0, ws_ctr = 0;       // streaming form: per-XCD ring of row-transformed samples; counters
