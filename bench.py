@@ -72,7 +72,7 @@ def write_traffic(pmc_dir: str, launch_cs: int = 4096, out_path: str | None = No
     """Reduces the four rocprofv3 --pmc runs of ``TRAFFIC_COMMANDS`` (CSV output under ``pmc_dir``) to
     ``profiles/traffic.json``: per fused-path kernel, FETCH_SIZE and WRITE_SIZE (KiB per dispatch, averaged over
     dispatches), each scaled by copy bytes / counter reading of the 1 GiB device copy; keyed by the kernel
-    sources' hash.  The default launch shape (64 samples x 64 channels) gives ``launch_cs`` channel-samples."""
+    sources' hash.  The default launch shape (128 samples x 32 channels) gives ``launch_cs`` channel-samples."""
     import collections
     import csv
 

@@ -82,10 +82,10 @@ typedef struct {
   double cell_lambda;       /* grid cell size in wavelengths (> 0) */
   int32_t fft_mode;         /* moff_fft_mode */
   int32_t acc_mode;         /* moff_acc_mode */
-  int32_t time_block;       /* samples per fused launch block (0 = library default, 64) */
+  int32_t time_block;       /* samples per fused launch block (0 = library default, 128) */
   int32_t volt_format;      /* moff_volt_format */
-  int32_t chans_per_block;  /* channels per fused launch block (0 = library default, 64) */
-  int32_t time_group;       /* samples per row-pass workgroup (0 = library default, 8) */
+  int32_t chans_per_block;  /* channels per fused launch block (0 = library default, 32) */
+  int32_t time_group;       /* samples per row-pass workgroup (0 = library default, 16) */
   int32_t kernel_mode;      /* moff_kernel_mode; Jones needs n_pol = 2 and the FP32 transform */
   int32_t n_tap;            /* E-field image taps per channel, 0..8 (moff_set_taps) */
 } moff_plan_desc;
