@@ -221,9 +221,10 @@ __device__ __forceinline__ void row_band(const RowArgs &a, int band, int t_lo, i
   constexpr int TS = row_stride(N);   // even: rows start on 16-byte boundaries
   static_assert(TS >= N + PP::RMAX - 1, "row stride too small for the padded layout");
   constexpr int HB = band_rows_ce(N, P);             // rows per band
-  // tap groups whose loads are issued together: 8 where LDS bounds the occupancy anyway (power-of-two n), 4 for
-  // mixed-radix n, whose occupancy is bounded by registers
-  constexpr int GCH = (N & (N - 1)) == 0 ? 8 : 4;
+  // tap groups whose loads are issued together; for power-of-two n the first batch's loads are issued before the
+  // band-grid clear, so that the clear and its barrier hide their latency (mixed-radix n lack the registers)
+  constexpr int GCH = 4;
+  constexpr bool EARLY = (N & (N - 1)) == 0;
 
   const Band *bp = a.bands + band;
   struct {
@@ -285,8 +286,28 @@ __device__ __forceinline__ void row_band(const RowArgs &a, int band, int t_lo, i
   uint32_t nxt = 0u;
   if (pre8 && t_lo < t_hi) nxt = fetch_volt_rec<P>(vrow_of(t_lo), 0, my_ant).x;
 
+  // one batch of tap groups: metadata and packed kernels (global loads)
+  auto load_batch = [&](int g, uint32_t (&m)[GCH], float2 (&w)[GCH][PL]) {
+#pragma unroll
+    for (int k = 0; k < GCH; ++k) {
+      const bool ok = g + k < gc;   // uniform: groups past the wave's last are not scattered
+      m[k] = ok ? a.meta[(g0 + g + k) * 64 + lane] : 0u;
+#pragma unroll
+      for (int p = 0; p < PL; ++p) w[k][p] = make_float2(0.f, 0.f);
+      if (ok) load_taps<PL>(a.wk + ((g0 + g + k) * 64 + lane) * PL, w[k]);
+    }
+  };
+
   for (int t = t_lo; t < t_hi; ++t) {
     if constexpr (SCAT) {
+      // the int8 record loaded after the previous sample's scatter: waiting for it also waits for that sample's
+      // stores (vector memory operations complete in order), as the scatter's loads would
+      uint32_t m0[GCH];
+      float2 w0[GCH][PL];
+      if constexpr (EARLY) {
+        if (pre8) put_volt_rec<P>(vtab, 0, threadIdx.x, make_uint4(nxt, 0u, 0u, 0u));
+        load_batch(0, m0, w0);
+      }
       // clear the band grid (16-byte stores over the whole contiguous region, unrolled: no loop between the
       // previous sample's stores and the record write below)
       {
@@ -298,12 +319,9 @@ __device__ __forceinline__ void row_band(const RowArgs &a, int band, int t_lo, i
           if (NCLR % kThreads == 0 || i < NCLR) g4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
         }
       }
-      // the int8 record loaded after the previous sample's scatter: waiting for it also waits for the previous
-      // sample's stores (vector memory operations complete in order), as the scatter's loads below would, so the
-      // wait comes after the clear
-      if (pre8)
-        put_volt_rec<P>(vtab, 0, threadIdx.x, make_uint4(nxt, 0u, 0u, 0u));
-      else if (my_ant >= 0)
+      if constexpr (!EARLY)
+        if (pre8) put_volt_rec<P>(vtab, 0, threadIdx.x, make_uint4(nxt, 0u, 0u, 0u));
+      if (!pre8 && my_ant >= 0)
         put_volt_rec<P>(vtab, a.volt_fmt, threadIdx.x, fetch_volt_rec<P>(vrow_of(t), a.volt_fmt, my_ant));
       for (int i = threadIdx.x + kThreads; i < bcnt; i += kThreads)
         put_volt_rec<P>(vtab, a.volt_fmt, i, fetch_volt_rec<P>(vrow_of(t), a.volt_fmt, blist[i]));
@@ -311,18 +329,7 @@ __device__ __forceinline__ void row_band(const RowArgs &a, int band, int t_lo, i
       // deterministic scatter: this wavefront's tap groups, one tap per lane, 64 distinct cells per group;
       // the loads of GCH groups are issued before any of them is used
       {
-        for (int g = 0; g < gc; g += GCH) {
-          uint32_t m[GCH];
-          float2 w[GCH][PL];
-#pragma unroll
-          for (int k = 0; k < GCH; ++k) {
-            const bool ok = g + k < gc;   // uniform: groups past the wave's last are not scattered
-            m[k] = ok ? a.meta[(g0 + g + k) * 64 + lane] : 0u;
-#pragma unroll
-            for (int p = 0; p < PL; ++p)
-              w[k][p] = make_float2(0.f, 0.f);
-            if (ok) load_taps<PL>(a.wk + ((g0 + g + k) * 64 + lane) * PL, w[k]);
-          }
+        auto scatter_batch = [&](int g, const uint32_t (&m)[GCH], const float2 (&w)[GCH][PL]) {
           // voltages of the GCH groups' taps from the LDS table or the voltage row (the loads are branch-free, so
           // all GCH are in flight together; an empty lane reads antenna 0 and adds it with zero weights)
           float2 e[GCH][P];
@@ -333,6 +340,17 @@ __device__ __forceinline__ void row_band(const RowArgs &a, int band, int t_lo, i
 #pragma unroll
           for (int k = 0; k < GCH; ++k)
             if (g + k < gc) scatter_tap(m[k], w[k], e[k]);
+        };
+        int g = 0;
+        if constexpr (EARLY) {
+          if (gc > 0) scatter_batch(0, m0, w0);
+          g = GCH;
+        }
+        for (; g < gc; g += GCH) {
+          uint32_t m[GCH];
+          float2 w[GCH][PL];
+          load_batch(g, m, w);
+          scatter_batch(g, m, w);
         }
       }
       __syncthreads();
