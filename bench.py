@@ -7,7 +7,7 @@ integration: zero the accumulator, grid + 2-D FFT + products for all 128 x 16384
 (moff_correlate), and the read-out of the 128 images (moff_read_image).  Voltages (17.2 GB) and kernels are
 resident in HBM before the timed region starts.
 
-Prints one JSON line.  ``--gpus N`` with N > 1 exits: this build runs on one GPU.
+Prints one JSON line.  ``--gpus N`` with N > 1 exits: the hot path runs on one GPU.
 """
 from __future__ import annotations
 
@@ -56,14 +56,14 @@ def _traffic(kernel: str, launch_cs: int):
     return k.get("bytes_per_launch")
 
 
-TRAFFIC_COMMANDS = [
-    "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_FETCH_SIZE -o run -- python3 -u bench.py "
+TRAFFIC_COMMANDS = [   # {dir}: the directory given to --write-traffic
+    "rocprofv3 --pmc FETCH_SIZE --output-format csv -d {dir}/pmc_FETCH_SIZE -o run -- python3 -u bench.py "
     "--time 512 --steps 1 --warmup 1 --no-cpu-baseline --eager",
-    "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_WRITE_SIZE -o run -- python3 -u bench.py "
+    "rocprofv3 --pmc WRITE_SIZE --output-format csv -d {dir}/pmc_WRITE_SIZE -o run -- python3 -u bench.py "
     "--time 512 --steps 1 --warmup 1 --no-cpu-baseline --eager",
-    "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmccopy_FETCH_SIZE -o run -- python3 -u bench.py "
+    "rocprofv3 --pmc FETCH_SIZE --output-format csv -d {dir}/pmccopy_FETCH_SIZE -o run -- python3 -u bench.py "
     "--calibrate-copy",
-    "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmccopy_WRITE_SIZE -o run -- python3 -u bench.py "
+    "rocprofv3 --pmc WRITE_SIZE --output-format csv -d {dir}/pmccopy_WRITE_SIZE -o run -- python3 -u bench.py "
     "--calibrate-copy",
 ]
 
@@ -103,7 +103,7 @@ def write_traffic(pmc_dir: str, launch_cs: int = 4096, out_path: str | None = No
          "note": "rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE per dispatch (KiB), each scaled by what the counter reads "
                  "for a plain 1 GiB device copy (FETCH x%.3f, WRITE x%.3f)" % (scale["FETCH_SIZE"],
                                                                               scale["WRITE_SIZE"]),
-         "commands": TRAFFIC_COMMANDS, "kernels": kernels}
+         "commands": [c.format(dir=pmc_dir) for c in TRAFFIC_COMMANDS], "kernels": kernels}
     with open(out_path or os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
         json.dump(d, fh, indent=1)
         fh.write("\n")
@@ -197,8 +197,8 @@ def main():
         print(json.dumps(write_traffic(args.write_traffic), indent=1))
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs the MOFF hot path on one GPU only (asked for --gpus {args.gpus}); "
-              "multi-GPU sharding is a design note, not part of this build.", file=sys.stderr)
+        print(f"bench.py: the MOFF hot path runs on one GPU only (asked for --gpus {args.gpus}); "
+              "sharding across GPUs is described in the design notes, not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -59,7 +59,7 @@ typedef enum {
   MOFF_E_INVALID = 1,     /* bad argument: null pointer, odd K, footprint outside the grid, bad size */
   MOFF_E_BUDGET = 2,      /* workspace smaller than moff_workspace_size */
   MOFF_E_DEVICE = 3,      /* a HIP call or kernel launch failed */
-  MOFF_E_UNSUPPORTED = 4, /* valid request this build does not implement (e.g. a grid size with a prime > 5) */
+  MOFF_E_UNSUPPORTED = 4, /* valid request the library does not implement (e.g. a grid size with a prime > 5) */
   MOFF_E_STATE = 5        /* call out of order: not bound, kernels not set */
 } moff_status;
 

@@ -143,7 +143,7 @@ moff_status build_plan(const moff_plan_desc &d, Plan &p, std::string *err);
 // Launch blocks and the row-transform buffer for a launch shape; returns the workspace bytes it needs.
 size_t layout_blocks(Plan &p, int t_block, int chans_per_block, int t_group);
 
-// True if this build has an FFT pipeline for grid size n.
+// True if the library has an FFT pipeline for grid size n.
 bool fft_size_supported(int n);
 int band_rows_for(int n, int P);
 int cols_for(int n);
