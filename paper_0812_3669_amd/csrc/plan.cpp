@@ -180,11 +180,21 @@ moff_status build_plan(const moff_plan_desc &d, Plan &p, std::string *err) {
   p.grp_kidx.clear();
   p.grp_chan.clear();
   std::vector<int32_t> last_used;
+  std::vector<std::vector<int32_t>> lists;   // antennas of each band of the channel, ascending
   for (int c = 0; c < C; ++c) {
     Chan &ch = p.chans[c];
     const int n = ch.n, h = ch.band_rows;
     ch.band_first = (int32_t)p.bands.size();
     const int b_lo = ch.jmin / h, b_hi = ch.jmax / h;
+    // antennas whose footprint rows [j0, j0+K-1] meet a band (boundary antennas appear in both bands): bands
+    // j0 / h .. (j0 + K - 1) / h, filled in ascending antenna order
+    lists.resize((size_t)(b_hi - b_lo + 1));
+    for (auto &l : lists) l.clear();
+    for (int a = 0; a < A; ++a) {
+      const int j0 = p.origin[((size_t)c * A + a) * 2];
+      for (int b = std::max(b_lo, j0 / h); b <= std::min(b_hi, (j0 + K - 1) / h); ++b)
+        lists[(size_t)(b - b_lo)].push_back(a);
+    }
     for (int b = b_lo; b <= b_hi; ++b) {
       Band bd{};
       bd.chan = c;
@@ -192,11 +202,8 @@ moff_status build_plan(const moff_plan_desc &d, Plan &p, std::string *err) {
       bd.rows = std::min(h, n - bd.row0);
       bd.r_lo = std::max(bd.row0, ch.jmin);
       bd.r_hi = std::min(bd.row0 + bd.rows - 1, ch.jmax);
-      // antennas whose footprint rows [j0, j0+K-1] meet the band (boundary antennas appear in both bands)
-      for (int a = 0; a < A; ++a) {
-        const int j0 = p.origin[((size_t)c * A + a) * 2];
-        if (j0 <= bd.row0 + bd.rows - 1 && j0 + K - 1 >= bd.row0) p.band_ant.push_back(a);
-      }
+      const std::vector<int32_t> &bl = lists[(size_t)(b - b_lo)];
+      p.band_ant.insert(p.band_ant.end(), bl.begin(), bl.end());
       const int32_t lo = p.band_ptr.back(), hi = (int32_t)p.band_ant.size();
       p.band_ptr.push_back(hi);
       bd.ant_off = lo;
@@ -212,7 +219,9 @@ moff_status build_plan(const moff_plan_desc &d, Plan &p, std::string *err) {
         last_used.assign((size_t)bd.rows * ts, -1);
         std::vector<uint64_t> used;      // per group: bit 16 q + k set when lane 16 q + k is taken
         std::vector<int32_t> count;
-        int64_t first_open = 0;
+        // per bank key: the first group with a free lane for that key (earlier groups have none, so first fit
+        // may start there)
+        int64_t first_free[16] = {};
         for (int e = lo; e < hi; ++e) {
           const int a = p.band_ant[e];
           const int j0 = p.origin[((size_t)c * A + a) * 2], i0 = p.origin[((size_t)c * A + a) * 2 + 1];
@@ -222,7 +231,7 @@ moff_status build_plan(const moff_plan_desc &d, Plan &p, std::string *err) {
             for (int x = 0; x < K; ++x) {
               const int cell = r * ts + i0 + x;   // element offset in a pol's band grid in LDS
               const int key = cell & 15;
-              int64_t g = std::max<int64_t>(first_open, (int64_t)last_used[cell] + 1);
+              int64_t g = std::max<int64_t>(first_free[key], (int64_t)last_used[cell] + 1);
               int lane = -1;
               for (;; ++g) {
                 if (g == (int64_t)count.size()) {
@@ -245,7 +254,9 @@ moff_status build_plan(const moff_plan_desc &d, Plan &p, std::string *err) {
               used[g] |= (uint64_t)1 << lane;
               ++count[g];
               last_used[cell] = (int32_t)g;
-              while (first_open < (int64_t)count.size() && count[first_open] == kGroupLanes) ++first_open;
+              const uint64_t key_lanes = 0x0001000100010001ull << key;
+              while (first_free[key] < (int64_t)count.size() && (used[first_free[key]] & key_lanes) == key_lanes)
+                ++first_free[key];
             }
           }
         }
@@ -260,13 +271,14 @@ moff_status build_plan(const moff_plan_desc &d, Plan &p, std::string *err) {
           for (int l = 0; l < kGroupLanes; ++l) {
             if (gm[l] != kEmptyTap) continue;
             const int key = l & 15;
-            int cell = key;
-            for (bool used = true; used && cell < bd.rows * ts;) {
-              used = (cell / ts) % kWaves != w;
-              for (int u = 0; u < n_taken[key]; ++u) used |= taken[key][u] == cell;
-              if (used) cell += 16;
-            }
-            if (cell >= bd.rows * ts) return fail(err, MOFF_E_INVALID, "no free cell for an empty tap lane");
+            int cell = -1;
+            for (int r = w; r < bd.rows && cell < 0; r += kWaves)   // this wavefront's rows
+              for (int cand = r * ts + ((key - r * ts) & 15); cand < (r + 1) * ts && cell < 0; cand += 16) {
+                bool used = false;
+                for (int u = 0; u < n_taken[key]; ++u) used |= taken[key][u] == cand;
+                if (!used) cell = cand;
+              }
+            if (cell < 0) return fail(err, MOFF_E_INVALID, "no free cell for an empty tap lane");
             taken[key][n_taken[key]++] = cell;
             gm[l] = (uint32_t)cell;
           }
