@@ -183,6 +183,8 @@ def main():
     ap.add_argument("--eager", action="store_true", help="launch kernel by kernel instead of replaying a HIP graph")
     ap.add_argument("--calibrate-copy", action="store_true", help="run a 1 GiB device copy (PMC calibration)")
     ap.add_argument("--write-traffic", metavar="DIR", help="write profiles/traffic.json from the PMC runs under DIR")
+    ap.add_argument("--calibrate-peaks", action="store_true",
+                    help="measure the FP32 vector FMA and FP16 matrix-core issue rates (moff_probe)")
     ap.add_argument("--pipeline", choices=["two_pass", "stream"], default="two_pass",
                     help="row/column exchange of the fused path: two kernels through HBM, or one persistent "
                          "launch per grid size streaming through each XCD's cache")
@@ -227,6 +229,21 @@ def main():
             e1.synchronize()
             rates[name] = round(10 * moved / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
         print(json.dumps({"calibrate_copy_bytes": nbytes, "launches": 3, "hbm_gbps": rates}))
+        return
+
+    if args.calibrate_peaks:
+        # measured ceilings beside the published ones: 8 x 256 workgroups per kind, 10 timed launches each
+        out = torch.empty(2048 * 256, dtype=torch.float32, device=dev)
+        res = {}
+        for kind, name, iters in ((0, "fp32_vector_fma_tflops", 4096), (1, "f16_mfma_tflops", 2048)):
+            api.probe(kind, 2048, iters, out)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            flops = sum(api.probe(kind, 2048, iters, out) for _ in range(10))
+            e1.record()
+            e1.synchronize()
+            res[name] = round(flops / (e0.elapsed_time(e1) * 1e-3) / 1e12, 1)
+        print(json.dumps(res))
         return
 
     if args.workload == "serving":

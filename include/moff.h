@@ -226,6 +226,14 @@ moff_status moff_profile(moff_plan_t plan, int32_t enable);
 moff_status moff_profile_read(moff_plan_t plan, int32_t kind, double *total_ms, int64_t *launches,
                               int64_t *channel_samples);
 
+/* Issue-rate probes (measurement only, no plan): kind 0 runs `blocks` workgroups of 256 threads, each thread
+ * `iters` iterations of 8 independent FP32 FMA chains (blocks x 256 x iters x 16 flops); kind 1 runs `blocks`
+ * workgroups of 4 wavefronts, each wavefront `iters` x 4 independent v_mfma_f32_16x16x32_f16 (blocks x 4 x iters
+ * x 4 x 16384 flops).  d_out: caller-owned device float [blocks x 256], one value per thread (the work is not
+ * optimised away).  Enqueues on `stream`; the caller times it.  MOFF_E_INVALID for blocks or iters < 1, a NULL
+ * d_out or an unknown kind. */
+moff_status moff_probe(int32_t kind, int32_t blocks, int32_t iters, float *d_out, void *stream);
+
 void moff_plan_destroy(moff_plan_t plan);
 const char *moff_status_str(moff_status s);
 /* Text of the most recent error on this thread ("" if none). */

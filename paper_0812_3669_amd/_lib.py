@@ -52,6 +52,7 @@ _SIGS = {
     "moff_correlate": ([_P, _P, C.c_int64, _P, _P], C.c_int),
     "moff_read_image": ([_P, _P, C.c_int64, C.c_int32, _P, _P], C.c_int),
     "moff_debug_unpack": ([_P, _P, _P, _P], C.c_int),
+    "moff_probe": ([C.c_int32, C.c_int32, C.c_int32, _P, _P], C.c_int),
     "moff_debug_tile_counts": ([_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int32)], C.c_int),
     "moff_debug_tiles": ([_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),
     "moff_workspace_size_for": ([_P, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)], C.c_int),

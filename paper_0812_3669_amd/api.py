@@ -339,6 +339,16 @@ class Plan:
         return origin, ptr, ant[: ne.value], rows
 
 
+def probe(kind: int, blocks: int, iters: int, out, stream=None):
+    """Enqueues an issue-rate probe (``moff_probe``): kind 0 FP32 vector FMAs, kind 1 FP16 matrix-core
+    instructions; ``out`` is a device float tensor of blocks x 256 elements.  Returns the flops it performs."""
+    lib = _lib.load()
+    if out.numel() < blocks * 256 or not out.is_cuda:
+        raise ValueError("out must be a device tensor of blocks x 256 floats")
+    _check(lib.moff_probe(kind, blocks, iters, _ptr(out), _stream_handle(stream)), "probe")
+    return blocks * 256 * iters * 16 if kind == 0 else blocks * 4 * iters * 4 * 16384
+
+
 def plan_for(cfg, geo, **kw) -> "Plan":
     """Plan for a workload description (``configs.Config``) and its geometry (``synth.Geometry``)."""
     return Plan(geo.ant_xy_m, geo.freqs_hz, geo.grid_n, n_pol=cfg.n_pol, ksize=cfg.ksize,
