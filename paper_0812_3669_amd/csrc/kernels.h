@@ -322,11 +322,12 @@ hipError_t launch_stream(int n, int P, int accm, bool jones, const StreamArgs &a
 // precision form (256^2 grids, two pols; kernels_mfma.hip)
 constexpr size_t kMfmaTableBytes = (size_t)17 * 2 * 3 * 64 * 8 * 2;
 size_t rows_mfma_lds_bytes(int band_ants, int volt_fmt);
-// Issue-rate probes (kernels_probe.hip): kind 0 FP32 vector FMAs, kind 1 FP16 matrix-core instructions.
-hipError_t launch_probe(int kind, int blocks, int iters, float *out, hipStream_t st);
 size_t cols_mfma_lds_bytes();
 hipError_t launch_mfma_table(uint16_t *tab, int bf16, hipStream_t st);
 hipError_t launch_rows_mfma(int bf16, const RowArgs &a, const uint16_t *table, int grid, hipStream_t st);
 hipError_t launch_cols_mfma(int bf16, int accm, const ColArgs &a, const uint16_t *table, int grid, hipStream_t st);
+
+// Issue-rate probes (kernels_probe.hip): kind 0 FP32 vector FMAs, kind 1 FP16 matrix-core instructions.
+hipError_t launch_probe(int kind, int blocks, int iters, float *out, hipStream_t st);
 
 }  // namespace moff
