@@ -158,8 +158,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
   }
 }
 
+// Two waves per SIMD: unbounded, the BF16 form took 248 VGPRs + 16 AGPRs and ran one wave per SIMD; under the
+// bound it fits 246 VGPRs without spilling.
 template <bool BF16, int ACC>
-__global__ __launch_bounds__(kThreads) void k_cols_mfma(ColArgs a, const uint16_t *table) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_cols_mfma(ColArgs a, const uint16_t *table) {
   extern __shared__ float4 smem4[];
   float2 *xs = reinterpret_cast<float2 *>(smem4);          // [16][MTS]: transform p * 8 + col
   float *ys = reinterpret_cast<float *>(xs + 16 * MTS);
