@@ -24,6 +24,12 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP32_VECTOR = 157.3e12    # MI355X published FP32 vector peak (packed FP32), FLOP/s
 PEAK_HBM = 8.0e12              # MI355X HBM3E, B/s
+PEAK_MFMA_16 = 2.5e15          # MI355X published dense FP16 / BF16 matrix-core peak, FLOP/s
+# Matrix-core form: a 256-point transform is two radix-16 stages, each 16 complex 16-point DFTs done as real
+# GEMMs (4096 complex MACs = 32768 flops per stage), once per split product (FP16 hi/lo: 3, BF16 hi/mid/lo: 6).
+# rocprofv3 SQ_INSTS_VALU_MFMA_MOPS_F16 / _BF16 x 512 reads the same count per launch.
+MFMA_FLOPS_PER_TRANSFORM = 2 * 16 * 16 * 16 * 8
+SPLIT_PRODUCTS = {"split_fp16": 3, "split_bf16": 6}
 
 
 KERNEL_SOURCES = ("kernels.hip", "kernels_mfma.hip", "kernels.h", "fft_radix.h", "fft_sizes.h", "mfma_fft.h")
@@ -319,13 +325,22 @@ def main():
         return 8.0 * A * P * K * K + fft_half if kind == 0 else fft_half + 16.0 * n * n
 
     names = {0: "k_rows", 1: "k_cols", 2: "k_stream"}
+    split = args.fft in SPLIT_PRODUCTS
+    if split:
+        # the matrix-core passes transform every row of the touched bands and every column (256^2, two pols)
+        names = {0: "k_rows_mfma", 1: "k_cols_mfma"}
+        _, band_ptr, _, band_rows = plan.debug_tiles()
+        assert len(set(band_rows.tolist())) == 1 and set(plan.grid_n) == {256}
+        per_transform = MFMA_FLOPS_PER_TRANSFORM * SPLIT_PRODUCTS[args.fft]
+        mfma_step = {0: (len(band_ptr) - 1) * int(band_rows[0]) * P * T * per_transform,
+                     1: cfg.n_chan * 256 * P * T * per_transform}
     kt = {}
     for kind in (0, 1, 2):
         tot_ms, launches, kcs = plan.profile_read(kind)
         if launches == 0:
             continue
         # the profiled step covers every channel for T samples; split its channel-samples by grid size
-        step_flops = sum(T * pass_flops(kind, n) for n in plan.grid_n)
+        step_flops = mfma_step[kind] if split else sum(T * pass_flops(kind, n) for n in plan.grid_n)
         kt[kind] = dict(ms=tot_ms, launches=launches, cs=kcs, flops=step_flops * kcs / (T * cfg.n_chan))
     dom = max(kt, key=lambda k: kt[k]["ms"])
     d = kt[dom]
@@ -333,10 +348,11 @@ def main():
     per_launch_flops = d["flops"] / max(d["launches"], 1)
     achieved = per_launch_flops / (avg_ms / 1e3)
     tot_ms_all = sum(v["ms"] for v in kt.values())
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP32_VECTOR,
+    peak = PEAK_MFMA_16 if split else PEAK_FP32_VECTOR
+    roofline = {"bound": "mfma" if split else "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
+                "unit": "TFLOP/s", "frac": achieved / peak,
                 "traffic": _traffic(names[dom], round(d["cs"] / max(d["launches"], 1)))
-                if args.workload == "headline" else None,
+                if args.workload == "headline" and not split else None,
                 "kernel": names[dom], "avg_launch_ms": avg_ms,
                 "kernel_share": {names[k]: kt[k]["ms"] / tot_ms_all for k in kt}}
     algo_flops_step = sum(T * cfg.flops_per_cs(n) for n in plan.grid_n)
