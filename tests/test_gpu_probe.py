@@ -1,0 +1,59 @@
+"""The issue-rate probes behind the measured ceilings (``moff_probe``): each kernel performs the work it reports.
+The FMA probe's per-thread result is replayed in float32 on the host; the matrix-core probe's against the
+16x16x32 product of its operands in the documented lane layout (A: lane l holds row l % 16, k = 8 (l / 16) + i;
+B: lane l holds column l % 16, k = 8 (l / 16) + i; D: lane l holds rows 4 (l / 16) + i of column l % 16)."""
+import numpy as np
+import pytest
+import torch
+
+from paper_0812_3669_amd import api
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _run(kind, blocks, iters):
+    out = torch.full((blocks * 256,), float("nan"), dtype=torch.float32, device=DEV)
+    print(f"probe kind={kind} blocks={blocks} iters={iters}", flush=True)
+    flops = api.probe(kind, blocks, iters, out)
+    torch.cuda.synchronize()
+    return flops, out.cpu().numpy()
+
+
+def test_fma_probe_matches_a_float32_replay():
+    blocks, iters = 3, 37
+    flops, got = _run(0, blocks, iters)
+    assert flops == blocks * 256 * iters * 16
+    tid = np.arange(256, dtype=np.int64)
+    b = np.float32(0.5) + np.float32(1e-3) * (tid & 7).astype(np.float32)
+    c = np.float32(1e-6) * (1 + (tid & 3)).astype(np.float32)
+    bc = b.astype(np.float64) * c.astype(np.float64)              # exact product of two float32
+    a = (tid[:, None] + np.arange(8)[None, :]).astype(np.float32)
+    for _ in range(iters):
+        a = (a.astype(np.float64) + bc[:, None]).astype(np.float32)
+    s = np.zeros(256, dtype=np.float32)
+    for k in range(8):
+        s = s + a[:, k]
+    want = np.tile(s, blocks)
+    np.testing.assert_allclose(got, want, rtol=1e-5, atol=1e-6)
+
+
+def test_mfma_probe_matches_the_tile_product():
+    blocks = 2
+    flops1, got1 = _run(1, blocks, 1)
+    flops3, got3 = _run(1, blocks, 3)
+    assert flops1 == blocks * 4 * 1 * 4 * 16384 and flops3 == 3 * flops1
+    lane = np.arange(64)
+    x = np.array([[np.float16(np.float32(0.001) * np.float32((l + k) & 7)) for k in range(8)] for l in lane])
+    y = np.array([[np.float16(np.float32(0.002) * np.float32((3 * l + k) & 7)) for k in range(8)] for l in lane])
+    A = np.zeros((16, 32))
+    B = np.zeros((32, 16))
+    for l in lane:
+        for i in range(8):
+            A[l % 16, 8 * (l // 16) + i] = float(x[l, i])
+            B[8 * (l // 16) + i, l % 16] = float(y[l, i])
+    D = A @ B
+    per_lane = np.array([4 * sum(D[4 * (l // 16) + i, l % 16] for i in range(4)) for l in lane])
+    want1 = np.tile(per_lane, 4 * blocks)
+    np.testing.assert_allclose(got1, want1, rtol=1e-5, atol=1e-9)
+    np.testing.assert_allclose(got3, 3 * want1, rtol=1e-5, atol=1e-9)
