@@ -31,11 +31,13 @@ def _run_fused(plan, volts, n_time=None):
     return imgs, acc
 
 
-def _check_images(imgs, ref, tol=TOL, label=""):
+def _check_images(imgs, ref, tol=TOL, label="", report=False):
     worst = 0.0
     for c in range(len(ref)):
         e = ora.relative_errors(imgs[c], ref[c])
         worst = max(worst, float(e.max()))
+        if report:
+            print(f"{label} channel {c}: per-image errors " + " ".join(f"{x:.2e}" for x in np.ravel(e)), flush=True)
         assert np.all(e <= tol), f"{label} channel {c}: per-product errors {e}"
     return worst
 
@@ -275,17 +277,19 @@ def test_graph_replay_shapes_and_autotune():
 # ---------------------------------------------------------------------------------------------------------
 # precision form: both FFT stages on the matrix cores with split FP16 / BF16 products
 # ---------------------------------------------------------------------------------------------------------
-@pytest.mark.parametrize("mode", [api.FFT_SPLIT_FP16, api.FFT_SPLIT_BF16])
+@pytest.mark.parametrize("mode", [api.FFT_FP32, api.FFT_SPLIT_FP16, api.FFT_SPLIT_BF16])
 @pytest.mark.parametrize("acc_mode", [api.ACC_FP32, api.ACC_FP64_COMP])
 def test_split_precision_transform(mode, acc_mode):
+    """The split FP16 / BF16 matrix-core transform against the oracle, beside the FP32 transform on the same
+    inputs; prints the per-image errors (XX, YY, XY, YX of each channel)."""
     cfg = _small(256, C=2, A=90, T=6, seed=7)
     geo, kern, volts = synth.workload(cfg)
     plan = api.plan_for(cfg, geo, fft_mode=mode, acc_mode=acc_mode).bind(DEV)
     plan.set_kernels(torch.from_numpy(kern).to(DEV))
     imgs, _ = _run_fused(plan, volts)
     ref = ora.image(volts, kern, geo.ant_xy_m, geo.freqs_hz, geo.grid_n, cfg.cell_lambda)
-    worst = _check_images(imgs, ref, label=f"split mode {mode}")
-    print(f"split mode {mode} acc {acc_mode}: worst per-image error {worst:.2e}")
+    worst = _check_images(imgs, ref, label=f"fft mode {mode} acc {acc_mode}", report=True)
+    print(f"fft mode {mode} acc {acc_mode}: worst per-image error {worst:.2e}")
 
 
 # ---------------------------------------------------------------------------------------------------------
