@@ -74,11 +74,11 @@ TRAFFIC_COMMANDS = [   # {dir}: the directory given to --write-traffic
 ]
 
 
-def write_traffic(pmc_dir: str, launch_cs: int = 4096, out_path: str | None = None) -> dict:
+def write_traffic(pmc_dir: str, launch_cs: int = 8192, out_path: str | None = None) -> dict:
     """Reduces the four rocprofv3 --pmc runs of ``TRAFFIC_COMMANDS`` (CSV output under ``pmc_dir``) to
     ``profiles/traffic.json``: per fused-path kernel, FETCH_SIZE and WRITE_SIZE (KiB per dispatch, averaged over
     dispatches), each scaled by copy bytes / counter reading of the 1 GiB device copy; keyed by the kernel
-    sources' hash.  The default launch shape (128 samples x 32 channels) gives ``launch_cs`` channel-samples."""
+    sources' hash.  The default launch shape (256 samples x 32 channels) gives ``launch_cs`` channel-samples."""
     import collections
     import csv
 
@@ -266,8 +266,9 @@ def main():
     acc_mode = api.ACC_FP64_COMP if args.acc == "fp64" else api.ACC_FP32
     fft_mode = {"fp32": api.FFT_FP32, "split_fp16": api.FFT_SPLIT_FP16, "split_bf16": api.FFT_SPLIT_BF16}[args.fft]
     plan = api.plan_for(cfg, geo, acc_mode=acc_mode, fft_mode=fft_mode)
-    room = max(plan.workspace_bytes_for(tb, cpb) for tb in (8, 16, 32, 64) for cpb in (4, 8, 16, 32, 64, 128)) \
-        if args.autotune else None
+    # room for every shape the autotuner tries, up to 16384 channel-samples per launch
+    room = max(plan.workspace_bytes_for(tb, cpb) for tb in (8, 16, 32, 64, 128, 256)
+               for cpb in (4, 8, 16, 32, 64, 128) if tb * cpb <= 16384) if args.autotune else None
     plan.bind(dev, workspace_bytes=room)
     plan.set_kernels(torch.from_numpy(kern_np).to(dev))
     plan.set_pipeline(api.PIPELINE_STREAM if args.pipeline == "stream" else api.PIPELINE_TWO_PASS)

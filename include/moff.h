@@ -82,10 +82,10 @@ typedef struct {
   double cell_lambda;       /* grid cell size in wavelengths (> 0) */
   int32_t fft_mode;         /* moff_fft_mode */
   int32_t acc_mode;         /* moff_acc_mode */
-  int32_t time_block;       /* samples per fused launch block (0 = library default, 128) */
+  int32_t time_block;       /* samples per fused launch block (0 = library default, 256) */
   int32_t volt_format;      /* moff_volt_format */
   int32_t chans_per_block;  /* channels per fused launch block (0 = library default, 32) */
-  int32_t time_group;       /* samples per row-pass workgroup (0 = library default, 16) */
+  int32_t time_group;       /* samples per row-pass workgroup (0 = library default, 32) */
   int32_t kernel_mode;      /* moff_kernel_mode; Jones needs n_pol = 2 and the FP32 transform */
   int32_t n_tap;            /* E-field image taps per channel, 0..8 (moff_set_taps) */
 } moff_plan_desc;
@@ -160,8 +160,10 @@ moff_status moff_get_launch_shape(moff_plan_t plan, int32_t *time_block, int32_t
                                   int32_t *time_group);
 
 /* Autotuner.  Times moff_correlate of n_t samples of d_volt for candidate launch shapes that fit the bound
- * workspace (d_acc is used as scratch and left holding garbage), keeps the fastest and returns it with its time
- * per call in ms.  Blocks the calling host thread (it synchronises the stream). */
+ * workspace: the plan's current shape first, then time blocks of 8-256 samples x 4-128 channels x row groups of
+ * 2-64 samples (d_acc is used as scratch and left holding garbage); keeps the fastest and returns it with its
+ * time per call in ms, so the result is never slower than the current shape on this input.  Blocks the calling
+ * host thread (it synchronises the stream). */
 moff_status moff_autotune(moff_plan_t plan, const void *d_volt, int64_t n_t, void *d_acc, void *stream,
                           int32_t *time_block, int32_t *chans_per_block, int32_t *time_group, double *best_ms);
 

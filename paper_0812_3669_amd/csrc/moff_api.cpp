@@ -3,10 +3,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "kernels.h"
 #include "moff.h"
@@ -781,39 +783,39 @@ moff_status moff_autotune(moff_plan_t plan, const void *d_volt, int64_t n_t, voi
   if (s) return s;
   if (p.profiling) return set_err(MOFF_E_STATE, "autotune while kernel timing is on");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  static const int tbs[] = {8, 16, 32, 64};
+  static const int tbs[] = {8, 16, 32, 64, 128, 256};
   static const int cpbs[] = {4, 8, 16, 32, 64, 128};
   static const int tgs[] = {2, 4, 8, 16, 32, 64};
+  const int tb0 = p.t_block, cpb0 = p.chans_per_block, tg0 = p.t_group;
+  // the current shape first, so that the result is never a shape slower than the one the plan had
+  std::vector<std::array<int, 3>> cands{{tb0, cpb0, tg0}};
+  for (int tb : tbs)
+    for (int cpb : cpbs)
+      for (int tg : tgs)
+        if (tg <= tb && !(tb == tb0 && cpb == cpb0 && tg == tg0)) cands.push_back({tb, cpb, tg});
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0), "event");
   HIP_TRY(hipEventCreate(&e1), "event");
-  const int tb0 = p.t_block, cpb0 = p.chans_per_block, tg0 = p.t_group;
   double best = 1e300;
   int btb = tb0, bcpb = cpb0, btg = tg0;
   moff_status res = MOFF_OK;
-  for (int tb : tbs) {
-    for (int cpb : cpbs) {
-      for (int tg : tgs) {
-        if (tg > tb) continue;
-        if (moff::layout_blocks(p, tb, cpb, tg) > p.ws_bound) continue;
-        float ms = 0.f;
-        if (enqueue_correlate(p, d_volt, n_t, d_acc, st) != MOFF_OK) { res = MOFF_E_DEVICE; break; }
-        hipError_t e = hipEventRecord(e0, st);
-        if (e == hipSuccess && enqueue_correlate(p, d_volt, n_t, d_acc, st) != MOFF_OK) e = hipErrorUnknown;
-        if (e == hipSuccess) e = hipEventRecord(e1, st);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        if (e != hipSuccess) { res = hip_fail(e, "autotune timing"); break; }
-        if (ms < best) {
-          best = ms;
-          btb = tb;
-          bcpb = cpb;
-          btg = tg;
-        }
-      }
-      if (res) break;
+  for (const auto &c : cands) {
+    const int tb = c[0], cpb = c[1], tg = c[2];
+    if (moff::layout_blocks(p, tb, cpb, tg) > p.ws_bound) continue;
+    float ms = 0.f;
+    if (enqueue_correlate(p, d_volt, n_t, d_acc, st) != MOFF_OK) { res = MOFF_E_DEVICE; break; }
+    hipError_t e = hipEventRecord(e0, st);
+    if (e == hipSuccess && enqueue_correlate(p, d_volt, n_t, d_acc, st) != MOFF_OK) e = hipErrorUnknown;
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) { res = hip_fail(e, "autotune timing"); break; }
+    if (ms < best) {
+      best = ms;
+      btb = tb;
+      bcpb = cpb;
+      btg = tg;
     }
-    if (res) break;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

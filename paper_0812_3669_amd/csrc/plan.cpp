@@ -106,11 +106,12 @@ moff_status build_plan(const moff_plan_desc &d, Plan &p, std::string *err) {
   const int A = p.n_ant, C = p.n_chan, K = p.ksize, P = p.n_pol;
   // launch-block shape of the fused path (defaults; MOFF_T_BLOCK, MOFF_T_GROUP, MOFF_CHANS_PER_BLOCK override)
   if (d.chans_per_block < 0 || d.time_group < 0) return fail(err, MOFF_E_INVALID, "launch shape must be >= 0");
-  // defaults: 128 samples x 32 channels per launch block, 16 samples per row-pass workgroup, measured best on
-  // MI355X for the 2048-antenna 256^2 and the 4096-antenna per-channel-size workloads (4096 channel-samples per
-  // launch; 128-sample blocks halve the accumulator updates of 64-sample ones)
-  const int tb = d.time_block > 0 ? d.time_block : env_int("MOFF_T_BLOCK", 128, 1, 4096);
-  const int tg = d.time_group > 0 ? d.time_group : env_int("MOFF_T_GROUP", 16, 1, 4096);
+  // defaults: 256 samples x 32 channels per launch block, 32 samples per row-pass workgroup, measured best on
+  // MI355X for the 2048-antenna 256^2 workload and neutral-to-better for the 4096-antenna per-channel-size one
+  // (8192 channel-samples per launch; each doubling of the block halves the accumulator updates; 512-sample or
+  // 64-channel blocks gain nothing more for twice the exchange buffer)
+  const int tb = d.time_block > 0 ? d.time_block : env_int("MOFF_T_BLOCK", 256, 1, 4096);
+  const int tg = d.time_group > 0 ? d.time_group : env_int("MOFF_T_GROUP", 32, 1, 4096);
   const int cpb = d.chans_per_block > 0 ? d.chans_per_block : env_int("MOFF_CHANS_PER_BLOCK", 32, 1, 1 << 20);
 
   // ---- per-channel grid size and footprints ------------------------------------------------------------
