@@ -92,7 +92,9 @@ typedef struct {
 
 /* Host only.  Validates the description, computes every antenna's footprint per channel, bins antennas into
  * grid row bands (an antenna whose footprint straddles a band boundary is listed in both bands: the paper's
- * module-boundary copies, Section 5) and lays out the workspace.  *out receives a new plan. */
+ * module-boundary copies, Section 5) and lays out the workspace.  *out receives a new plan.  Channels are
+ * binned on host threads (environment MOFF_PLAN_THREADS, default the host's threads up to 16); the plan is the
+ * same for every thread count. */
 moff_status moff_plan(const moff_plan_desc *desc, moff_plan_t *out);
 
 /* Bytes of device workspace the plan needs (>= 256-byte aligned sections). */

@@ -1,10 +1,14 @@
 // Host plan: geometry, row-band binning and tap groups of the gridding step (Eq. m6 step 2), launch blocks and
 // the device workspace layout.  No HIP calls here.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <string>
+#include <thread>
+#include <vector>
 
 #include "fft_sizes.h"
 #include "moff_plan.h"
@@ -61,6 +65,134 @@ int smallest_supported_size(int need) {
   for (int v : ok)
     if (v >= need) return v;
   return 0;
+}
+
+// Row bands, band antenna lists and tap groups of one channel, with offsets local to the channel (the caller
+// appends channels in order and shifts the offsets).  Reads the footprint origins and the channel's grid
+// geometry only, so channels build independently.
+struct ChanBuild {
+  std::vector<Band> bands;
+  std::vector<int32_t> band_end;   // end of each band's antenna list in `ant`
+  std::vector<int32_t> ant;
+  std::vector<uint32_t> meta;
+  std::vector<int32_t> kidx;
+  int64_t n_groups = 0;
+  int32_t max_ants = 0;
+  moff_status st = MOFF_OK;
+  std::string err;
+};
+
+void build_channel(const Plan &p, int c, int A, int K, ChanBuild &out) {
+  const Chan &ch = p.chans[c];
+  const int n = ch.n, h = ch.band_rows;
+  const int b_lo = ch.jmin / h, b_hi = ch.jmax / h;
+  // antennas whose footprint rows [j0, j0+K-1] meet a band (boundary antennas appear in both bands): bands
+  // j0 / h .. (j0 + K - 1) / h, filled in ascending antenna order
+  std::vector<std::vector<int32_t>> lists((size_t)(b_hi - b_lo + 1));
+  for (int a = 0; a < A; ++a) {
+    const int j0 = p.origin[((size_t)c * A + a) * 2];
+    for (int b = std::max(b_lo, j0 / h); b <= std::min(b_hi, (j0 + K - 1) / h); ++b)
+      lists[(size_t)(b - b_lo)].push_back(a);
+  }
+  std::vector<int32_t> last_used;
+  for (int b = b_lo; b <= b_hi; ++b) {
+    Band bd{};
+    bd.chan = c;
+    bd.row0 = b * h;
+    bd.rows = std::min(h, n - bd.row0);
+    bd.r_lo = std::max(bd.row0, ch.jmin);
+    bd.r_hi = std::min(bd.row0 + bd.rows - 1, ch.jmax);
+    const std::vector<int32_t> &bl = lists[(size_t)(b - b_lo)];
+    const int32_t lo = (int32_t)out.ant.size();
+    out.ant.insert(out.ant.end(), bl.begin(), bl.end());
+    const int32_t hi = (int32_t)out.ant.size();
+    out.band_end.push_back(hi);
+    bd.ant_off = lo;
+    bd.ant_cnt = hi - lo;
+    if (row_stages_volts(n)) out.max_ants = std::max(out.max_ants, hi - lo);
+    // tap groups per wavefront: 64 taps on 64 distinct cells per group, antennas ascending, first fit, so every
+    // cell receives its contributions in ascending antenna order (deterministic sums, no atomics).  Lane
+    // 16 q + k of a group holds a tap whose LDS word offset is k mod 16, so the 16 lanes a quarter-wave
+    // presents to the LDS at once hit 16 different bank pairs.
+    const int ts = row_stride(n);
+    for (int w = 0; w < kWaves; ++w) {
+      const int64_t g0 = out.n_groups;
+      last_used.assign((size_t)bd.rows * ts, -1);
+      std::vector<uint64_t> used;      // per group: bit 16 q + k set when lane 16 q + k is taken
+      std::vector<int32_t> count;
+      // per bank key: the first group with a free lane for that key (earlier groups have none, so first fit
+      // may start there)
+      int64_t first_free[16] = {};
+      for (int e = lo; e < hi; ++e) {
+        const int a = out.ant[e];
+        const int j0 = p.origin[((size_t)c * A + a) * 2], i0 = p.origin[((size_t)c * A + a) * 2 + 1];
+        for (int y = 0; y < K; ++y) {
+          const int r = j0 + y - bd.row0;
+          if (r < 0 || r >= bd.rows || (r % kWaves) != w) continue;
+          for (int x = 0; x < K; ++x) {
+            const int cell = r * ts + i0 + x;   // element offset in a pol's band grid in LDS
+            const int key = cell & 15;
+            int64_t g = std::max<int64_t>(first_free[key], (int64_t)last_used[cell] + 1);
+            int lane = -1;
+            for (;; ++g) {
+              if (g == (int64_t)count.size()) {
+                count.push_back(0);
+                used.push_back(0);
+                out.meta.resize(out.meta.size() + kGroupLanes, kEmptyTap);
+                out.kidx.resize(out.kidx.size() + kGroupLanes, -1);
+              }
+              for (int q = 0; q < 4; ++q)
+                if (!((used[g] >> (16 * q + key)) & 1)) {
+                  lane = 16 * q + key;
+                  break;
+                }
+              if (lane >= 0) break;
+            }
+            const size_t slot = (size_t)(g0 + g) * kGroupLanes + lane;
+            out.meta[slot] = ((uint32_t)(row_stages_volts(n) ? e - lo : a) << 16) | (uint32_t)cell;
+            out.kidx[slot] = (a * K + y) * K + x;
+            used[g] |= (uint64_t)1 << lane;
+            ++count[g];
+            last_used[cell] = (int32_t)g;
+            const uint64_t key_lanes = 0x0001000100010001ull << key;
+            while (first_free[key] < (int64_t)count.size() && (used[first_free[key]] & key_lanes) == key_lanes)
+              ++first_free[key];
+          }
+        }
+      }
+      // empty lanes get a cell in one of this wavefront's rows (other wavefronts scatter into theirs at the same
+      // time) that no other lane of their group uses (same bank key), and zero weights (kidx -1): they add 0
+      // there, so the row pass needs no per-lane emptiness test
+      for (size_t g = 0; g < count.size(); ++g) {
+        uint32_t *gm = out.meta.data() + (size_t)(g0 + (int64_t)g) * kGroupLanes;
+        int taken[16][kGroupLanes / 16], n_taken[16] = {};   // cells in use per bank key (4 lanes per key)
+        for (int l = 0; l < kGroupLanes; ++l)
+          if (gm[l] != kEmptyTap) taken[l & 15][n_taken[l & 15]++] = (int)(gm[l] & 0xFFFFu);
+        for (int l = 0; l < kGroupLanes; ++l) {
+          if (gm[l] != kEmptyTap) continue;
+          const int key = l & 15;
+          int cell = -1;
+          for (int r = w; r < bd.rows && cell < 0; r += kWaves)   // this wavefront's rows
+            for (int cand = r * ts + ((key - r * ts) & 15); cand < (r + 1) * ts && cell < 0; cand += 16) {
+              bool busy = false;
+              for (int u = 0; u < n_taken[key]; ++u) busy |= taken[key][u] == cand;
+              if (!busy) cell = cand;
+            }
+          if (cell < 0) {
+            out.st = MOFF_E_INVALID;
+            out.err = "no free cell for an empty tap lane";
+            return;
+          }
+          taken[key][n_taken[key]++] = cell;
+          gm[l] = (uint32_t)cell;
+        }
+      }
+      bd.grp_off[w] = g0;
+      bd.grp_cnt[w] = (int32_t)count.size();
+      out.n_groups += (int64_t)count.size();
+    }
+    out.bands.push_back(bd);
+  }
 }
 
 moff_status build_plan(const moff_plan_desc &d, Plan &p, std::string *err) {
@@ -173,125 +305,69 @@ moff_status build_plan(const moff_plan_desc &d, Plan &p, std::string *err) {
   }
 
   // ---- row bands, band antenna lists and tap groups ------------------------------------------------------
+  // channels build on worker threads (MOFF_PLAN_THREADS, default: the host's threads up to 16) and are placed
+  // in channel order, so the plan does not depend on the thread count
+  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+  const int n_thr = std::min(C, env_int("MOFF_PLAN_THREADS", (int)std::min(hw, 16u), 1, 256));
+  auto parallel_channels = [&](const std::function<void(int)> &fn) {
+    std::atomic<int> next{0};
+    auto work = [&]() {
+      for (int c; (c = next.fetch_add(1)) < C;) fn(c);
+    };
+    std::vector<std::thread> pool;
+    for (int t = 1; t < n_thr; ++t) pool.emplace_back(work);
+    work();
+    for (auto &t : pool) t.join();
+  };
+  std::vector<ChanBuild> built((size_t)C);
+  parallel_channels([&](int c) {
+    try {
+      build_channel(p, c, A, K, built[(size_t)c]);
+    } catch (const std::exception &ex) {
+      built[(size_t)c].st = MOFF_E_INVALID;
+      built[(size_t)c].err = std::string("plan build failed: ") + ex.what();
+    }
+  });
+  // offsets of each channel's bands, antenna entries and groups; the arrays are sized once and filled in parallel
+  std::vector<int64_t> ant_at((size_t)C + 1, 0), grp_at((size_t)C + 1, 0);
+  for (int c = 0; c < C; ++c) {
+    const ChanBuild &cb = built[(size_t)c];
+    if (cb.st != MOFF_OK) return fail(err, cb.st, cb.err);
+    ant_at[(size_t)c + 1] = ant_at[(size_t)c] + (int64_t)cb.ant.size();
+    grp_at[(size_t)c + 1] = grp_at[(size_t)c] + cb.n_groups;
+  }
+  if (ant_at[(size_t)C] > INT32_MAX) return fail(err, MOFF_E_UNSUPPORTED, "too many band antenna entries");
   p.bands.clear();
   p.max_band_ants = 0;
   p.band_ptr.assign(1, 0);
-  p.band_ant.clear();
-  p.grp_meta.clear();
-  p.grp_kidx.clear();
-  p.grp_chan.clear();
-  std::vector<int32_t> last_used;
-  std::vector<std::vector<int32_t>> lists;   // antennas of each band of the channel, ascending
+  p.n_groups = grp_at[(size_t)C];
   for (int c = 0; c < C; ++c) {
+    const ChanBuild &cb = built[(size_t)c];
     Chan &ch = p.chans[c];
-    const int n = ch.n, h = ch.band_rows;
+    const int32_t ant_base = (int32_t)ant_at[(size_t)c];
     ch.band_first = (int32_t)p.bands.size();
-    const int b_lo = ch.jmin / h, b_hi = ch.jmax / h;
-    // antennas whose footprint rows [j0, j0+K-1] meet a band (boundary antennas appear in both bands): bands
-    // j0 / h .. (j0 + K - 1) / h, filled in ascending antenna order
-    lists.resize((size_t)(b_hi - b_lo + 1));
-    for (auto &l : lists) l.clear();
-    for (int a = 0; a < A; ++a) {
-      const int j0 = p.origin[((size_t)c * A + a) * 2];
-      for (int b = std::max(b_lo, j0 / h); b <= std::min(b_hi, (j0 + K - 1) / h); ++b)
-        lists[(size_t)(b - b_lo)].push_back(a);
-    }
-    for (int b = b_lo; b <= b_hi; ++b) {
-      Band bd{};
-      bd.chan = c;
-      bd.row0 = b * h;
-      bd.rows = std::min(h, n - bd.row0);
-      bd.r_lo = std::max(bd.row0, ch.jmin);
-      bd.r_hi = std::min(bd.row0 + bd.rows - 1, ch.jmax);
-      const std::vector<int32_t> &bl = lists[(size_t)(b - b_lo)];
-      p.band_ant.insert(p.band_ant.end(), bl.begin(), bl.end());
-      const int32_t lo = p.band_ptr.back(), hi = (int32_t)p.band_ant.size();
-      p.band_ptr.push_back(hi);
-      bd.ant_off = lo;
-      bd.ant_cnt = hi - lo;
-      if (row_stages_volts(n)) p.max_band_ants = std::max(p.max_band_ants, hi - lo);
-      // tap groups per wavefront: 64 taps on 64 distinct cells per group, antennas ascending, first fit, so every
-      // cell receives its contributions in ascending antenna order (deterministic sums, no atomics).  Lane
-      // 16 q + k of a group holds a tap whose LDS word offset is k mod 16, so the 16 lanes a quarter-wave
-      // presents to the LDS at once hit 16 different bank pairs.
-      const int ts = row_stride(n);
-      for (int w = 0; w < kWaves; ++w) {
-        const int64_t g0 = p.n_groups;
-        last_used.assign((size_t)bd.rows * ts, -1);
-        std::vector<uint64_t> used;      // per group: bit 16 q + k set when lane 16 q + k is taken
-        std::vector<int32_t> count;
-        // per bank key: the first group with a free lane for that key (earlier groups have none, so first fit
-        // may start there)
-        int64_t first_free[16] = {};
-        for (int e = lo; e < hi; ++e) {
-          const int a = p.band_ant[e];
-          const int j0 = p.origin[((size_t)c * A + a) * 2], i0 = p.origin[((size_t)c * A + a) * 2 + 1];
-          for (int y = 0; y < K; ++y) {
-            const int r = j0 + y - bd.row0;
-            if (r < 0 || r >= bd.rows || (r % kWaves) != w) continue;
-            for (int x = 0; x < K; ++x) {
-              const int cell = r * ts + i0 + x;   // element offset in a pol's band grid in LDS
-              const int key = cell & 15;
-              int64_t g = std::max<int64_t>(first_free[key], (int64_t)last_used[cell] + 1);
-              int lane = -1;
-              for (;; ++g) {
-                if (g == (int64_t)count.size()) {
-                  count.push_back(0);
-                  used.push_back(0);
-                  p.grp_meta.resize(p.grp_meta.size() + kGroupLanes, kEmptyTap);
-                  p.grp_kidx.resize(p.grp_kidx.size() + kGroupLanes, -1);
-                  p.grp_chan.push_back(c);
-                }
-                for (int q = 0; q < 4; ++q)
-                  if (!((used[g] >> (16 * q + key)) & 1)) {
-                    lane = 16 * q + key;
-                    break;
-                  }
-                if (lane >= 0) break;
-              }
-              const size_t slot = (size_t)(g0 + g) * kGroupLanes + lane;
-              p.grp_meta[slot] = ((uint32_t)(row_stages_volts(n) ? e - lo : a) << 16) | (uint32_t)cell;
-              p.grp_kidx[slot] = (a * K + y) * K + x;
-              used[g] |= (uint64_t)1 << lane;
-              ++count[g];
-              last_used[cell] = (int32_t)g;
-              const uint64_t key_lanes = 0x0001000100010001ull << key;
-              while (first_free[key] < (int64_t)count.size() && (used[first_free[key]] & key_lanes) == key_lanes)
-                ++first_free[key];
-            }
-          }
-        }
-        // empty lanes get a cell in one of this wavefront's rows (other wavefronts scatter into theirs at the same
-        // time) that no other lane of their group uses (same bank key), and zero weights (kidx -1): they add 0
-        // there, so the row pass needs no per-lane emptiness test
-        for (size_t g = 0; g < count.size(); ++g) {
-          uint32_t *gm = p.grp_meta.data() + (size_t)(g0 + (int64_t)g) * kGroupLanes;
-          int taken[16][kGroupLanes / 16], n_taken[16] = {};   // cells in use per bank key (4 lanes per key)
-          for (int l = 0; l < kGroupLanes; ++l)
-            if (gm[l] != kEmptyTap) taken[l & 15][n_taken[l & 15]++] = (int)(gm[l] & 0xFFFFu);
-          for (int l = 0; l < kGroupLanes; ++l) {
-            if (gm[l] != kEmptyTap) continue;
-            const int key = l & 15;
-            int cell = -1;
-            for (int r = w; r < bd.rows && cell < 0; r += kWaves)   // this wavefront's rows
-              for (int cand = r * ts + ((key - r * ts) & 15); cand < (r + 1) * ts && cell < 0; cand += 16) {
-                bool used = false;
-                for (int u = 0; u < n_taken[key]; ++u) used |= taken[key][u] == cand;
-                if (!used) cell = cand;
-              }
-            if (cell < 0) return fail(err, MOFF_E_INVALID, "no free cell for an empty tap lane");
-            taken[key][n_taken[key]++] = cell;
-            gm[l] = (uint32_t)cell;
-          }
-        }
-        bd.grp_off[w] = g0;
-        bd.grp_cnt[w] = (int32_t)count.size();
-        p.n_groups += (int64_t)count.size();
-      }
+    ch.band_count = (int32_t)cb.bands.size();
+    for (size_t b = 0; b < cb.bands.size(); ++b) {
+      Band bd = cb.bands[b];
+      bd.ant_off += ant_base;
+      for (int w = 0; w < kWaves; ++w) bd.grp_off[w] += grp_at[(size_t)c];
       p.bands.push_back(bd);
+      p.band_ptr.push_back(ant_base + cb.band_end[b]);
     }
-    ch.band_count = (int32_t)p.bands.size() - ch.band_first;
+    p.max_band_ants = std::max(p.max_band_ants, cb.max_ants);
   }
+  p.band_ant.assign((size_t)ant_at[(size_t)C], 0);
+  p.grp_meta.assign((size_t)p.n_groups * kGroupLanes, 0);
+  p.grp_kidx.assign((size_t)p.n_groups * kGroupLanes, 0);
+  p.grp_chan.assign((size_t)p.n_groups, 0);
+  parallel_channels([&](int c) {
+    ChanBuild &cb = built[(size_t)c];
+    std::copy(cb.ant.begin(), cb.ant.end(), p.band_ant.begin() + ant_at[(size_t)c]);
+    std::copy(cb.meta.begin(), cb.meta.end(), p.grp_meta.begin() + grp_at[(size_t)c] * kGroupLanes);
+    std::copy(cb.kidx.begin(), cb.kidx.end(), p.grp_kidx.begin() + grp_at[(size_t)c] * kGroupLanes);
+    std::fill(p.grp_chan.begin() + grp_at[(size_t)c], p.grp_chan.begin() + grp_at[(size_t)c + 1], c);
+    cb = ChanBuild();   // release the channel's copy
+  });
   if ((int64_t)p.bands.size() > INT32_MAX / 2) return fail(err, MOFF_E_UNSUPPORTED, "too many bands");
 
   // ---- workspace layout (launch blocks and the row-transform buffer last) -------------------------------

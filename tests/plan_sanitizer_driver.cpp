@@ -3,6 +3,7 @@
 #include "fft_sizes.h"
 #include "moff_plan.h"
 #include <cstdio>
+#include <cstdlib>
 #include <cmath>
 #include <random>
 #include <vector>
@@ -17,8 +18,26 @@ int run(int A, int C, int n, int K, double disk, int P, int ntap, int seed) {
   moff_plan_desc d{}; d.n_ant = A; d.n_pol = P; d.n_chan = C; d.ksize = K; d.ant_xy_m = xy.data(); d.freq_hz = f.data();
   d.grid_n = n > 0 ? gn.data() : nullptr; d.cell_lambda = 1.0; d.n_tap = ntap;
   moff::Plan p; std::string err;
+  setenv("MOFF_PLAN_THREADS", "1", 1);
   int s = moff::build_plan(d, p, &err);
   if (s) { printf("A=%d C=%d n=%d K=%d: status %d (%s)\n", A, C, n, K, s, err.c_str()); return s; }
+  // channels built on several threads give the same plan as one thread
+  moff::Plan q; std::string err2;
+  setenv("MOFF_PLAN_THREADS", "5", 1);
+  if (moff::build_plan(d, q, &err2) != 0) { printf("threaded build failed: %s\n", err2.c_str()); return 1; }
+  unsetenv("MOFF_PLAN_THREADS");
+  bool same = p.band_ptr == q.band_ptr && p.band_ant == q.band_ant && p.grp_meta == q.grp_meta &&
+              p.grp_kidx == q.grp_kidx && p.grp_chan == q.grp_chan && p.n_groups == q.n_groups &&
+              p.max_band_ants == q.max_band_ants && p.bands.size() == q.bands.size() && p.ws_total == q.ws_total;
+  for (size_t b = 0; same && b < p.bands.size(); ++b) {
+    const moff::Band &x = p.bands[b], &y = q.bands[b];
+    same = x.chan == y.chan && x.row0 == y.row0 && x.rows == y.rows && x.r_lo == y.r_lo && x.r_hi == y.r_hi &&
+           x.ant_off == y.ant_off && x.ant_cnt == y.ant_cnt;
+    for (int w = 0; same && w < moff::kWaves; ++w) same = x.grp_off[w] == y.grp_off[w] && x.grp_cnt[w] == y.grp_cnt[w];
+  }
+  for (size_t c = 0; same && c < p.chans.size(); ++c)
+    same = p.chans[c].band_first == q.chans[c].band_first && p.chans[c].band_count == q.chans[c].band_count;
+  if (!same) { printf("threaded plan differs from the one-thread plan\n"); return 1; }
   long taps = 0;
   for (auto k : p.grp_kidx) taps += (k >= 0);
   for (auto m : p.grp_meta) if (m == moff::kEmptyTap) { printf("unfilled lane\n"); return 1; }

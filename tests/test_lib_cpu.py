@@ -201,7 +201,7 @@ def test_plan_builder_under_host_sanitizers(tmp_path):
         pytest.skip("g++ not available")
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     exe = str(tmp_path / "plan_sanitizer")
-    cmd = [gxx, "-O1", "-g", "-std=c++17", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+    cmd = [gxx, "-O1", "-g", "-std=c++17", "-pthread", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
            "-I" + os.path.join(root, "include"), "-I" + os.path.join(root, "paper_0812_3669_amd", "csrc"),
            os.path.join(root, "tests", "plan_sanitizer_driver.cpp"),
            os.path.join(root, "paper_0812_3669_amd", "csrc", "plan.cpp"), "-o", exe]
