@@ -6,6 +6,7 @@
 #include <array>
 #include <cmath>
 #include <cstring>
+#include <exception>
 #include <new>
 #include <string>
 #include <vector>
@@ -331,7 +332,13 @@ moff_status moff_plan(const moff_plan_desc *desc, moff_plan_t *out) {
   moff_plan_s *h = new (std::nothrow) moff_plan_s();
   if (!h) return set_err(MOFF_E_INVALID, "out of host memory");
   std::string err;
-  moff_status s = moff::build_plan(*desc, h->p, &err);
+  moff_status s;
+  try {
+    s = moff::build_plan(*desc, h->p, &err);
+  } catch (const std::exception &ex) {   // host allocation or thread creation failed: no exception crosses the C ABI
+    s = MOFF_E_INVALID;
+    err = std::string("plan build failed on the host: ") + ex.what();
+  }
   if (s != MOFF_OK) {
     delete h;
     return set_err(s, err);

@@ -7,6 +7,7 @@
 #include <cstring>
 #include <functional>
 #include <string>
+#include <system_error>
 #include <thread>
 #include <vector>
 
@@ -315,7 +316,13 @@ moff_status build_plan(const moff_plan_desc &d, Plan &p, std::string *err) {
       for (int c; (c = next.fetch_add(1)) < C;) fn(c);
     };
     std::vector<std::thread> pool;
-    for (int t = 1; t < n_thr; ++t) pool.emplace_back(work);
+    for (int t = 1; t < n_thr; ++t) {
+      try {
+        pool.emplace_back(work);
+      } catch (const std::system_error &) {   // fewer threads: the calling thread takes the remaining channels
+        break;
+      }
+    }
     work();
     for (auto &t : pool) t.join();
   };
