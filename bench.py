@@ -331,7 +331,8 @@ def main():
         # the matrix-core passes transform every row of the touched bands and every column (256^2, two pols)
         names = {0: "k_rows_mfma", 1: "k_cols_mfma"}
         _, band_ptr, _, band_rows = plan.debug_tiles()
-        assert len(set(band_rows.tolist())) == 1 and set(plan.grid_n) == {256}
+        if len(set(band_rows.tolist())) != 1 or set(plan.grid_n) != {256}:
+            raise SystemExit("bench: the matrix-core flop count assumes 256^2 grids with one band height")
         per_transform = MFMA_FLOPS_PER_TRANSFORM * SPLIT_PRODUCTS[args.fft]
         mfma_step = {0: (len(band_ptr) - 1) * int(band_rows[0]) * P * T * per_transform,
                      1: cfg.n_chan * 256 * P * T * per_transform}
