@@ -166,6 +166,18 @@ def test_ragged_time_blocks_and_fp64_accumulator():
         _check_images(imgs, ref, label=f"acc mode {mode}")
 
 
+def test_default_shape_ragged_blocks():
+    """The library's default launch shape (256-sample x 32-channel blocks, 32-sample row groups) with a ragged
+    last time block (300 = 256 + 44 samples; its last row group holds 12) and a ragged last channel block
+    (35 = 32 + 3 channels): every pixel of every channel against the oracle."""
+    cfg = _small(64, C=35, A=30, T=300, seed=11)
+    geo, kern, volts, plan = _setup(cfg)
+    assert plan.launch_shape() == (256, 32, 32)
+    imgs, _ = _run_fused(plan, volts)
+    ref = ora.image(volts, kern, geo.ant_xy_m, geo.freqs_hz, geo.grid_n, cfg.cell_lambda)
+    _check_images(imgs, ref, label="default shape, ragged blocks")
+
+
 def test_plain_workload_channels():
     """The plain workload (256 antennas, 32 channels, 128^2, dual pol): all channels through the fused path,
     lowest and highest channel checked pixel by pixel over the first 512 samples."""
