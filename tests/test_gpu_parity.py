@@ -304,6 +304,22 @@ def test_split_precision_transform(mode, acc_mode):
     print(f"fft mode {mode} acc {acc_mode}: worst per-image error {worst:.2e}")
 
 
+@pytest.mark.parametrize("mode", [api.FFT_SPLIT_FP16, api.FFT_SPLIT_BF16])
+def test_split_precision_default_shape_ragged(mode):
+    """The matrix-core forms at the default launch shape with a ragged last time block (260 = 256 + 4 samples)
+    and a ragged last channel block (33 = 32 + 1 channels); the first channel and the one in the ragged block
+    against the oracle, every pixel."""
+    cfg = _small(256, C=33, A=40, T=260, seed=13)
+    geo, kern, volts = synth.workload(cfg)
+    plan = api.plan_for(cfg, geo, fft_mode=mode).bind(DEV)
+    assert plan.launch_shape() == (256, 32, 32)
+    plan.set_kernels(torch.from_numpy(kern).to(DEV))
+    imgs, _ = _run_fused(plan, volts)
+    sel = [0, cfg.n_chan - 1]
+    ref = ora.image(volts[:, sel], kern[sel], geo.ant_xy_m, geo.freqs_hz[sel], geo.grid_n[sel], cfg.cell_lambda)
+    _check_images([imgs[c] for c in sel], ref, label=f"split mode {mode}, ragged blocks", report=True)
+
+
 # ---------------------------------------------------------------------------------------------------------
 # the headline workload at full size, in the launch configuration the benchmark times
 # ---------------------------------------------------------------------------------------------------------
