@@ -21,12 +21,13 @@ def _series_err(gpu, ref):
     return float(np.abs(gpu - ref).max() / np.abs(ref).max())
 
 
-@pytest.mark.parametrize("P,n,M", [(2, 64, 3), (1, 128, 2)])
-def test_taps_and_calibration_sums(P, n, M):
-    cfg = configs.scaled(configs.PLAIN, index=500 + n, n_ant=40, n_pol=P, n_chan=3, n_time=20, ksize=4, grid_n=n,
+@pytest.mark.parametrize("P,n,M,T,tb", [(2, 64, 3, 20, 8), (1, 128, 2, 20, 8), (2, 64, 3, 300, 0)])
+def test_taps_and_calibration_sums(P, n, M, T, tb):
+    """tb = 0: the library's default launch shape (256-sample blocks: 300 samples end in a ragged block)."""
+    cfg = configs.scaled(configs.PLAIN, index=500 + n, n_ant=40, n_pol=P, n_chan=3, n_time=T, ksize=4, grid_n=n,
                          disk_lambda=0.6 * n)
     geo, kern, volts = synth.workload(cfg)
-    plan = api.plan_for(cfg, geo, n_tap=M, time_block=8).bind(DEV)
+    plan = api.plan_for(cfg, geo, n_tap=M, time_block=tb).bind(DEV)
     kd = torch.from_numpy(np.ascontiguousarray(kern)).to(DEV)
     plan.set_kernels(kd)
     rng = np.random.default_rng(n)
