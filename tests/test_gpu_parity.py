@@ -395,8 +395,10 @@ def _jones_kernels(kern, seed, leak=0.3):
     return J
 
 
-@pytest.mark.parametrize("n,K,A,C,T,tb", [(64, 4, 40, 2, 9, 0), (128, 6, 61, 2, 13, 4), (256, 4, 75, 1, 5, 0)])
+@pytest.mark.parametrize("n,K,A,C,T,tb", [(64, 4, 40, 2, 9, 0), (128, 6, 61, 2, 13, 4), (256, 4, 75, 1, 5, 0),
+                                          (64, 4, 30, 33, 300, 0)])
 def test_jones_kernels_fused(n, K, A, C, T, tb):
+    """tb = 0: the library's default launch shape; the last case ends in ragged time and channel blocks."""
     cfg = _small(n, A=A, C=C, T=T, K=K, seed=20 + n)
     geo, kern, volts = synth.workload(cfg)
     J = _jones_kernels(kern, seed=n)
