@@ -300,6 +300,9 @@ __device__ __forceinline__ void row_band(const RowArgs &a, int band, int t_lo, i
 
   for (int t = t_lo; t < t_hi; ++t) {
     if constexpr (SCAT) {
+      // wave priority 1 from the tap-group loads to the end of the scatter, 0 for the transforms and stores: a
+      // workgroup in its load phase issues ahead of one in its arithmetic phase on the same CU
+      __builtin_amdgcn_s_setprio(1);
       // the int8 record loaded after the previous sample's scatter: waiting for it also waits for that sample's
       // stores (vector memory operations complete in order), as the scatter's loads would
       uint32_t m0[GCH];
@@ -355,6 +358,7 @@ __device__ __forceinline__ void row_band(const RowArgs &a, int band, int t_lo, i
       }
       __syncthreads();
       if (pre8 && t + 1 < t_hi) nxt = fetch_volt_rec<P>(vrow_of(t + 1), 0, my_ant).x;
+      __builtin_amdgcn_s_setprio(0);
     } else {
       // ROW_FFT: load the band's touched rows from the staged grid
       for (int i = threadIdx.x; i < ntr * N; i += kThreads) {
