@@ -92,6 +92,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
   if (pre8 && t_lo < t_hi) nxt = fetch_volt_rec<MP>(vrow_of(t_lo), 0, my_ant).x;
 
   for (int t = t_lo; t < t_hi; ++t) {
+    // priority 1 while the wave loads and scatters, 0 for the transforms (as in the FP32 row pass)
+    __builtin_amdgcn_s_setprio(1);
     if (pre8) {
       if (t == t_lo) put_volt_rec<MP>(vtab, 0, threadIdx.x, make_uint4(nxt, 0u, 0u, 0u));
     } else if (my_ant >= 0) {
@@ -135,6 +137,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     }
     __syncthreads();
     if (pre8 && t + 1 < t_hi) nxt = fetch_volt_rec<MP>(vrow_of(t + 1), 0, my_ant).x;
+    __builtin_amdgcn_s_setprio(0);
     // 16 row transforms (pol p, band row r) = transform p * 8 + r; outputs back into the grid (its reads
     // finished at the barrier inside the FFT)
     fft256x16_mfma<BF16>(grid, MTS, ys, mats,
