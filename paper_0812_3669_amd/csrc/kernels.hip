@@ -647,8 +647,13 @@ __device__ __forceinline__ void col_group(const ColArgs &a, int c, int cg, int t
 }
 
 // Fused / staged column pass: one workgroup per (channel, column group), samples split over gridDim.y.
+// Fused dual-pol 256-point form with the FP64 (sum, carry) accumulator: the LDS allows 4 workgroups per CU, and
+// the 4-wave bound fits it in 128 VGPRs (4 waves per SIMD instead of 3).
 template <int N, int P, int W, int MODE, int ACC>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_cols(ColArgs a) {
+__global__ __launch_bounds__(kThreads)
+__attribute__((amdgpu_waves_per_eu(N == 256 && P == 2 && MODE == 0 && ACC == 1 ? 4 : 2,
+                                   N == 256 && P == 2 && MODE == 0 && ACC == 1 ? 4 : 8)))
+void k_cols(ColArgs a) {
   extern __shared__ float4 smem4[];
   float2 *buf = reinterpret_cast<float2 *>(smem4);   // [P][W][TS]
   float2 *tws = buf + P * W * Pipe<N>::TS;            // [2N] twiddle tables
