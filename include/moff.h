@@ -128,7 +128,9 @@ moff_status moff_set_kernels_phased(moff_plan_t plan, const void *d_kern, const 
 /* Staged path, step 2 (gridding): d_volt [n_t] samples -> d_grid [n_t] grids (layout above, fully written). */
 moff_status moff_grid(moff_plan_t plan, const void *d_volt, int64_t n_t, void *d_grid, void *stream);
 
-/* Staged path, step 3: in-place 2-D FFT of n_t grids into E-field images (FFT pixel order). */
+/* Staged path, step 3: in-place 2-D FFT of n_t grids into E-field images (FFT pixel order).  Every row and column
+ * of every channel's grid is transformed, so the grids may hold data anywhere (not only on the footprint rows that
+ * moff_grid writes). */
 moff_status moff_fft(moff_plan_t plan, void *d_grid, int64_t n_t, void *stream);
 
 /* Staged path, step 4: adds the polarisation products of n_t E-field images to the accumulator. */

@@ -43,6 +43,27 @@ def _ptr(t) -> C.c_void_p:
     return C.c_void_p(t.data_ptr())
 
 
+def _check_buffer(t, name: str, device, dtypes, nbytes: int):
+    """The C ABI takes raw pointers and trusts their extent, so every buffer passed to it is checked here first:
+    a torch tensor on the plan's device, contiguous, of one of ``dtypes`` and holding at least ``nbytes`` bytes.
+    Raises ValueError (TypeError for a non-tensor); nothing is enqueued then."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor, got {type(t).__name__}")
+    if device is None:
+        raise ValueError(f"{name}: the plan is not bound to a device (call bind() first)")
+    if t.device != torch.device(device):
+        raise ValueError(f"{name} must be on {device}, got {t.device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    dtypes = dtypes if isinstance(dtypes, (tuple, list)) else (dtypes,)
+    if t.dtype not in dtypes:
+        raise ValueError(f"{name} must have dtype {' or '.join(str(d) for d in dtypes)}, got {t.dtype}")
+    have = t.numel() * t.element_size()
+    if have < nbytes:
+        raise ValueError(f"{name} holds {have} bytes, the call needs {nbytes}")
+
+
 class Plan:
     """A MOFF correlation plan (geometry, band binning, workspace) for one array and channel set."""
 
@@ -71,6 +92,7 @@ class Plan:
         self._h = h
         self._ws = None
         self._kern_ref = None
+        self.device = None
         self.grid_n = []
         self.pix_off = []
         for c in range(self.n_chan):
@@ -136,13 +158,17 @@ class Plan:
         maps voltage pol q into grid p), the noise weight folded in.  phase: optional complex64 [C, A, P] that
         multiplies each voltage before gridding (phase-centre tracking)."""
         import torch
-        assert kern.dtype == torch.complex64 and kern.is_contiguous()
-        assert tuple(kern.shape) == self._kernel_shape(), kern.shape
+        shape = self._kernel_shape()
+        _check_buffer(kern, "kern", self.device, torch.complex64, int(np.prod(shape)) * 8)
+        if tuple(kern.shape) != shape:
+            raise ValueError(f"kern must have shape {shape}, got {tuple(kern.shape)}")
         if phase is None:
             _check(self.lib.moff_set_kernels(self._h, _ptr(kern), _stream_handle(stream)), "moff_set_kernels")
         else:
-            assert phase.dtype == torch.complex64 and phase.is_contiguous()
-            assert tuple(phase.shape) == (self.n_chan, self.n_ant, self.n_pol), phase.shape
+            pshape = (self.n_chan, self.n_ant, self.n_pol)
+            _check_buffer(phase, "phase", self.device, torch.complex64, int(np.prod(pshape)) * 8)
+            if tuple(phase.shape) != pshape:
+                raise ValueError(f"phase must have shape {pshape}, got {tuple(phase.shape)}")
             _check(self.lib.moff_set_kernels_phased(self._h, _ptr(kern), _ptr(phase), _stream_handle(stream)),
                    "moff_set_kernels_phased")
         self._kern_ref = (kern, phase)   # keep alive until the packing kernel has run
@@ -154,20 +180,31 @@ class Plan:
         elems = self.acc_bytes // (8 if dt == torch.float64 else 4)
         return torch.zeros(elems, dtype=dt, device=self.device)
 
+    def _sample_bytes(self) -> int:
+        """Bytes of one time sample of voltages (all channels, antennas and pols)."""
+        return self.n_chan * self.n_ant * self.n_pol * (2 if self.volt_format == VOLT_INT8 else 8)
+
     def _check_volts(self, volts, n_t):
         import torch
-        if self.volt_format == VOLT_INT8:
-            assert volts.dtype == torch.int8 and volts.shape[-1] == 2
-            per = self.n_chan * self.n_ant * self.n_pol * 2
-        else:
-            assert volts.dtype == torch.complex64
-            per = self.n_chan * self.n_ant * self.n_pol
-        assert volts.is_contiguous() and volts.numel() >= n_t * per, (volts.shape, n_t)
+        if n_t < 0:
+            raise ValueError(f"n_t must be >= 0, got {n_t}")
+        dt = torch.int8 if self.volt_format == VOLT_INT8 else torch.complex64
+        _check_buffer(volts, "volts", self.device, dt, n_t * self._sample_bytes())
+
+    def _check_acc(self, acc, name="acc"):
+        import torch
+        dt = torch.float64 if self.acc_mode == ACC_FP64_COMP else torch.float32
+        _check_buffer(acc, name, self.device, dt, self.acc_bytes)
+
+    def _grid_bytes(self, n_t: int) -> int:
+        """Bytes of n_t staged grids or E-field images (complex64, P * sum_c n_c^2 per sample)."""
+        return n_t * self.n_pol * self.pix_total * 8
 
     # ---- the hot path ---------------------------------------------------------------------------------------------
     def correlate(self, volts, acc, n_t: Optional[int] = None, stream=None):
         n_t = volts.shape[0] if n_t is None else n_t
         self._check_volts(volts, n_t)
+        self._check_acc(acc)
         _check(self.lib.moff_correlate(self._h, _ptr(volts), n_t, _ptr(acc), _stream_handle(stream)),
                "moff_correlate")
 
@@ -175,6 +212,7 @@ class Plan:
         """Same as correlate, replayed from a captured HIP graph (captured on first use per buffer set)."""
         n_t = volts.shape[0] if n_t is None else n_t
         self._check_volts(volts, n_t)
+        self._check_acc(acc)
         _check(self.lib.moff_correlate_graph(self._h, _ptr(volts), n_t, _ptr(acc), _stream_handle(stream)),
                "moff_correlate_graph")
 
@@ -185,7 +223,8 @@ class Plan:
         if pix.ndim == 2:
             pix = np.broadcast_to(pix, (self.n_chan,) + pix.shape)
         pix = np.ascontiguousarray(pix)
-        assert pix.shape == (self.n_chan, self.n_tap, 2), pix.shape
+        if pix.shape != (self.n_chan, self.n_tap, 2):
+            raise ValueError(f"pix must have shape {(self.n_chan, self.n_tap, 2)}, got {pix.shape}")
         self._tap_pix = pix
         _check(self.lib.moff_set_taps(self._h, pix.ctypes.data_as(C.POINTER(C.c_int32)), _stream_handle(stream)),
                "moff_set_taps")
@@ -197,21 +236,28 @@ class Plan:
 
     def correlate_tap(self, volts, acc, tap, n_t: Optional[int] = None, stream=None):
         """correlate plus the E-field image at the tapped pixels of every sample: tap complex64 [T, C, n_tap, P]."""
+        import torch
         n_t = volts.shape[0] if n_t is None else n_t
         self._check_volts(volts, n_t)
-        assert tap.is_contiguous() and tap.numel() >= n_t * self.n_chan * self.n_tap * self.n_pol
+        self._check_acc(acc)
+        _check_buffer(tap, "tap", self.device, torch.complex64, n_t * self.n_chan * self.n_tap * self.n_pol * 8)
         _check(self.lib.moff_correlate_tap(self._h, _ptr(volts), n_t, _ptr(acc), _ptr(tap), _stream_handle(stream)),
                "moff_correlate_tap")
 
+    @property
+    def cal_bytes(self) -> int:
+        return self._size(self.lib.moff_cal_size)
+
     def new_cal(self):
         import torch
-        b = C.c_size_t()
-        _check(self.lib.moff_cal_size(self._h, C.byref(b)), "moff_cal_size")
-        return torch.zeros(b.value // 8, dtype=torch.float64, device=self.device)
+        return torch.zeros(self.cal_bytes // 8, dtype=torch.float64, device=self.device)
 
     def cal_accumulate(self, volts, tap, cal, n_t: Optional[int] = None, stream=None):
+        import torch
         n_t = volts.shape[0] if n_t is None else n_t
         self._check_volts(volts, n_t)
+        _check_buffer(tap, "tap", self.device, torch.complex64, n_t * self.n_chan * self.n_tap * self.n_pol * 8)
+        _check_buffer(cal, "cal", self.device, torch.float64, self.cal_bytes)
         _check(self.lib.moff_cal_accumulate(self._h, _ptr(volts), _ptr(tap), n_t, _ptr(cal), _stream_handle(stream)),
                "moff_cal_accumulate")
 
@@ -229,6 +275,9 @@ class Plan:
         """-> (S, X, u), each complex128 [C, n_tap, A, P]: the per-antenna correlation with its gain applied,
         the sum of all visibilities not involving the antenna, and the gain-update factor."""
         import torch
+        _check_buffer(cal, "cal", self.device, torch.float64, self.cal_bytes)
+        kshape = (self.n_chan, self.n_ant, self.n_pol, self.ksize, self.ksize)
+        _check_buffer(kern, "kern", self.device, torch.complex64, int(np.prod(kshape)) * 8)
         shape = (3, self.n_chan, self.n_tap, self.n_ant, self.n_pol)
         out = torch.empty(shape, dtype=torch.complex128, device=self.device)
         _check(self.lib.moff_cal_solve(self._h, _ptr(cal), _ptr(kern), _ptr(out), _stream_handle(stream)),
@@ -258,6 +307,7 @@ class Plan:
         """Times candidate launch shapes on this input (acc is scratch); keeps and returns the fastest."""
         n_t = volts.shape[0] if n_t is None else n_t
         self._check_volts(volts, n_t)
+        self._check_acc(acc)
         tb, cpb, tg, ms = C.c_int32(), C.c_int32(), C.c_int32(), C.c_double()
         _check(self.lib.moff_autotune(self._h, _ptr(volts), n_t, _ptr(acc), _stream_handle(stream), C.byref(tb),
                                       C.byref(cpb), C.byref(tg), C.byref(ms)), "moff_autotune")
@@ -269,19 +319,30 @@ class Plan:
         self._check_volts(volts, n_t)
         if out is None:
             out = torch.empty(n_t * self.n_pol * self.pix_total, dtype=torch.complex64, device=self.device)
+        _check_buffer(out, "out", self.device, torch.complex64, self._grid_bytes(n_t))
         _check(self.lib.moff_grid(self._h, _ptr(volts), n_t, _ptr(out), _stream_handle(stream)), "moff_grid")
         return out
 
     def fft(self, grid, n_t: int, stream=None):
+        import torch
+        if n_t < 0:
+            raise ValueError(f"n_t must be >= 0, got {n_t}")
+        _check_buffer(grid, "grid", self.device, torch.complex64, self._grid_bytes(n_t))
         _check(self.lib.moff_fft(self._h, _ptr(grid), n_t, _stream_handle(stream)), "moff_fft")
         return grid
 
     def accumulate(self, efield, n_t: int, acc, stream=None):
+        import torch
+        if n_t < 0:
+            raise ValueError(f"n_t must be >= 0, got {n_t}")
+        _check_buffer(efield, "efield", self.device, torch.complex64, self._grid_bytes(n_t))
+        self._check_acc(acc)
         _check(self.lib.moff_accumulate(self._h, _ptr(efield), n_t, _ptr(acc), _stream_handle(stream)),
                "moff_accumulate")
 
     def read_image(self, acc, n_samples: int = 0, normalize: bool = False, stream=None, split: bool = True):
         import torch
+        self._check_acc(acc)
         img = torch.empty(self.n_prod * self.pix_total, dtype=torch.complex64, device=self.device)
         _check(self.lib.moff_read_image(self._h, _ptr(acc), n_samples, int(bool(normalize)), _ptr(img),
                                         _stream_handle(stream)), "moff_read_image")
@@ -321,6 +382,8 @@ class Plan:
     # ---- test hooks ------------------------------------------------------------------------------------------------
     def debug_unpack(self, volt_sample, stream=None):
         import torch
+        dt = torch.int8 if self.volt_format == VOLT_INT8 else torch.complex64
+        _check_buffer(volt_sample, "volt_sample", self.device, dt, self._sample_bytes())
         out = torch.empty(self.n_chan * self.n_ant * self.n_pol * 2, dtype=torch.float32, device=self.device)
         _check(self.lib.moff_debug_unpack(self._h, _ptr(volt_sample), _ptr(out), _stream_handle(stream)),
                "moff_debug_unpack")
@@ -342,9 +405,11 @@ class Plan:
 def probe(kind: int, blocks: int, iters: int, out, stream=None):
     """Enqueues an issue-rate probe (``moff_probe``): kind 0 FP32 vector FMAs, kind 1 FP16 matrix-core
     instructions; ``out`` is a device float tensor of blocks x 256 elements.  Returns the flops it performs."""
+    import torch
     lib = _lib.load()
-    if out.numel() < blocks * 256 or not out.is_cuda:
+    if not isinstance(out, torch.Tensor) or not out.is_cuda:
         raise ValueError("out must be a device tensor of blocks x 256 floats")
+    _check_buffer(out, "out", out.device, torch.float32, blocks * 256 * 4)
     _check(lib.moff_probe(kind, blocks, iters, _ptr(out), _stream_handle(stream)), "probe")
     return blocks * 256 * iters * 16 if kind == 0 else blocks * 4 * iters * 4 * 16384
 

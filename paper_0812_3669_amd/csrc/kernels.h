@@ -58,6 +58,7 @@ struct ColArgs {
   void *acc;                 // fused: accumulator
   int64_t sample_stride;
   int n_chan_block;          // fused: channels in the launch block (XCD-aware workgroup mapping)
+  int full_rows;             // staged FFT: every row of the column holds data (no footprint row range)
 };
 
 // XCD-aware workgroup mapping of the fused passes.  Workgroups are dispatched round-robin over the 8 XCDs

@@ -469,7 +469,7 @@ __device__ __forceinline__ void col_group(const ColArgs &a, int c, int cg, int t
   constexpr int PA = P == 2 ? 2 : 1;                  // accumulator reals per pixel and lane
 
   const int col0 = cg * W;
-  const int jmin = a.chans[c].jmin, jmax = a.chans[c].jmax;
+  const int jmin = a.full_rows ? 0 : a.chans[c].jmin, jmax = a.full_rows ? N - 1 : a.chans[c].jmax;
   const int64_t pstride = (int64_t)N * N;
 
   float acc[MBL][RL][PA];

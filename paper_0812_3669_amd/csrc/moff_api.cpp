@@ -131,8 +131,9 @@ moff_status ensure_overlap(moff::Plan &p) {
   return MOFF_OK;
 }
 
+struct Exchange;
 moff_status enqueue_two_pass(moff::Plan &p, const void *d_volt, int64_t n_t, void *d_acc, hipStream_t st, int c_lo,
-                             int c_hi, void *d_tap = nullptr);
+                             int c_hi, void *d_tap = nullptr, const Exchange *ex = nullptr);
 
 // Streaming form: per run of channels with one grid size, clear the counters and launch the persistent kernel
 // sized to the device's occupancy (all its workgroups resident at once).
@@ -188,19 +189,26 @@ moff_status enqueue_stream(moff::Plan &p, const void *d_volt, int64_t n_t, void 
   return MOFF_OK;
 }
 
+// Where the two-pass form puts the row-transformed grids of a launch block: by default the workspace's
+// exchange region (p.t_block samples of one of the plan's channel blocks); a caller can pass instead a
+// fixed buffer of `bytes`, and the launch blocks are cut (channels, then samples) so that one fits it.
+struct Exchange {
+  float2 *base;
+  size_t bytes;
+};
+
 // Two-pass form for the channels [c_lo, c_hi) (a union of launch blocks).
 moff_status enqueue_two_pass(moff::Plan &p, const void *d_volt, int64_t n_t, void *d_acc, hipStream_t st, int c_lo,
-                             int c_hi, void *d_tap) {
-  float2 *H0 = reinterpret_cast<float2 *>(ws(p, p.ws_h));
+                             int c_hi, void *d_tap, const Exchange *ex) {
+  float2 *H0 = ex ? ex->base : reinterpret_cast<float2 *>(ws(p, p.ws_h));
   const bool jones = is_jones(p);
   moff::RowArgs a = row_args(p, d_volt);
   moff::ColArgs ca{};
   ca.chans = d_chans(p);
   ca.acc = d_acc;
-  ca.t_block = p.t_block;
   // Overlap: the row passes run on an internal stream, block k into buffer k % 2, while the column pass of
   // block k - 1 runs on the caller's stream; events order rows(k) -> cols(k) and cols(k - 2) -> rows(k).
-  const bool dual = p.overlap != 0;
+  const bool dual = p.overlap != 0 && !ex;
   hipStream_t rs = st;
   if (dual) {
     moff_status r = ensure_overlap(p);
@@ -209,81 +217,107 @@ moff_status enqueue_two_pass(moff::Plan &p, const void *d_volt, int64_t n_t, voi
     HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(p.ev_fork), st), "fork event");
     HIP_TRY(hipStreamWaitEvent(rs, static_cast<hipEvent_t>(p.ev_fork), 0), "fork wait");
   }
+  const bool split = p.fft_mode != MOFF_FFT_FP32;
+  const int bf16 = p.fft_mode == MOFF_FFT_SPLIT_BF16;
+  const uint16_t *mtab = reinterpret_cast<const uint16_t *>(ws(p, p.ws_mfma));
   int64_t k = 0;
-  for (int64_t t0 = 0; t0 < n_t; t0 += p.t_block) {
-    const int nt = (int)std::min<int64_t>(p.t_block, n_t - t0);
-    for (const moff::Block &b : p.blocks) {
-      if (b.c0 < c_lo || b.c1 > c_hi) continue;
-      const int slot = dual ? (int)(k % 2) : 0;
-      float2 *H = H0 + (size_t)slot * (p.ws_h_bytes / sizeof(float2));
-      a.io = H;
-      ca.in = H;
-      if (dual && k >= 2)
-        HIP_TRY(hipStreamWaitEvent(rs, static_cast<hipEvent_t>(p.ev_cols[slot]), 0), "buffer reuse wait");
-      a.band_begin = band_begin(p, b);
-      a.n_bands = band_count(p, b);
-      a.c0 = b.c0;
-      a.n_chan_block = b.c1 - b.c0;
-      a.t0 = (int)t0;
-      a.nt = nt;
-      a.tw = d_tw(p, b.n);
-      const int tgroups = (nt + p.t_group - 1) / p.t_group;
-      const size_t lds = moff::rows_lds_bytes(b.n, p.n_pol, p.chans[b.c0].band_rows, p.max_band_ants, p.volt_format);
-      const int64_t cs = (int64_t)nt * (b.c1 - b.c0);
-      const bool split = p.fft_mode != MOFF_FFT_FP32;
-      const int bf16 = p.fft_mode == MOFF_FFT_SPLIT_BF16;
-      const uint16_t *mtab = reinterpret_cast<const uint16_t *>(ws(p, p.ws_mfma));
-      {
-        ProfScope ps(p, rs, 0, cs);
-        const int rgrid = moff::rows_xcd_grid(p, b, tgroups);
-        if (split)
-          HIP_TRY(moff::launch_rows_mfma(bf16, a, mtab, rgrid, rs), "row pass");
-        else
-          HIP_TRY(moff::launch_rows(b.n, p.n_pol, moff::ROW_MODE_FUSED, jones, a, rgrid, lds, rs), "row pass");
-        HIP_TRY(ps.done(), "profile event");
+  // one launch block: channels [b.c0, b.c1) x samples [t0, t0 + nt), the exchange holding `tblk` samples per channel
+  auto one_block = [&](const moff::Block &b, int64_t t0, int nt, int tblk) -> moff_status {
+    const int slot = dual ? (int)(k % 2) : 0;
+    float2 *H = H0 + (size_t)slot * (p.ws_h_bytes / sizeof(float2));
+    a.io = H;
+    ca.in = H;
+    a.t_block = ca.t_block = tblk;
+    if (dual && k >= 2)
+      HIP_TRY(hipStreamWaitEvent(rs, static_cast<hipEvent_t>(p.ev_cols[slot]), 0), "buffer reuse wait");
+    a.band_begin = band_begin(p, b);
+    a.n_bands = band_count(p, b);
+    a.c0 = b.c0;
+    a.n_chan_block = b.c1 - b.c0;
+    a.t0 = (int)t0;
+    a.nt = nt;
+    a.tw = d_tw(p, b.n);
+    const int tgroups = (nt + p.t_group - 1) / p.t_group;
+    const size_t lds = moff::rows_lds_bytes(b.n, p.n_pol, p.chans[b.c0].band_rows, p.max_band_ants, p.volt_format);
+    const int64_t cs = (int64_t)nt * (b.c1 - b.c0);
+    {
+      ProfScope ps(p, rs, 0, cs);
+      const int rgrid = moff::rows_xcd_grid(p, b, tgroups);
+      if (split)
+        HIP_TRY(moff::launch_rows_mfma(bf16, a, mtab, rgrid, rs), "row pass");
+      else
+        HIP_TRY(moff::launch_rows(b.n, p.n_pol, moff::ROW_MODE_FUSED, jones, a, rgrid, lds, rs), "row pass");
+      HIP_TRY(ps.done(), "profile event");
+    }
+    if (d_tap) {
+      // E-field image at the tapped pixels, from this block's row-transformed samples
+      moff::TapArgs ta{};
+      ta.chans = d_chans(p);
+      ta.h = H;
+      ta.tap_tw = reinterpret_cast<const float2 *>(ws(p, p.ws_tap_tw));
+      ta.tap_tw_off = reinterpret_cast<const int64_t *>(ws(p, p.ws_tap_twoff));
+      ta.tap_idx = reinterpret_cast<const int2 *>(ws(p, p.ws_tap_idx));
+      ta.out = static_cast<float2 *>(d_tap);
+      ta.c0 = b.c0;
+      ta.n_chan_block = b.c1 - b.c0;
+      ta.t0 = (int)t0;
+      ta.nt = nt;
+      ta.t_block = tblk;
+      ta.n_chan = p.n_chan;
+      ta.n_tap = p.n_tap;
+      ta.P = p.n_pol;
+      HIP_TRY(moff::launch_tap(ta, rs), "tap");
+    }
+    if (dual) {
+      HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(p.ev_rows[slot]), rs), "row event");
+      HIP_TRY(hipStreamWaitEvent(st, static_cast<hipEvent_t>(p.ev_rows[slot]), 0), "row wait");
+    }
+    const int W = p.chans[b.c0].cols;
+    ca.c0 = b.c0;
+    ca.t0 = (int)t0;
+    ca.nt = nt;
+    ca.tw = a.tw;
+    const int grid = moff::cols_xcd_grid(b, b.n / W);
+    ca.n_chan_block = b.c1 - b.c0;
+    {
+      ProfScope ps(p, st, 1, cs);
+      if (split)
+        HIP_TRY(moff::launch_cols_mfma(bf16, p.acc_mode, ca, mtab, grid, st), "column pass");
+      else
+        HIP_TRY(moff::launch_cols(b.n, p.n_pol, W, moff::COL_MODE_FUSED, p.acc_mode, ca, grid, 1,
+                                  moff::cols_lds_bytes(b.n, p.n_pol, W), st),
+                "column pass");
+      HIP_TRY(ps.done(), "profile event");
+    }
+    if (dual) HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(p.ev_cols[slot]), st), "column event");
+    ++k;
+    return MOFF_OK;
+  };
+  if (!ex) {
+    for (int64_t t0 = 0; t0 < n_t; t0 += p.t_block) {
+      const int nt = (int)std::min<int64_t>(p.t_block, n_t - t0);
+      for (const moff::Block &b : p.blocks) {
+        if (b.c0 < c_lo || b.c1 > c_hi) continue;
+        moff_status r = one_block(b, t0, nt, p.t_block);
+        if (r) return r;
       }
-      if (d_tap) {
-        // E-field image at the tapped pixels, from this block's row-transformed samples
-        moff::TapArgs ta{};
-        ta.chans = d_chans(p);
-        ta.h = H;
-        ta.tap_tw = reinterpret_cast<const float2 *>(ws(p, p.ws_tap_tw));
-        ta.tap_tw_off = reinterpret_cast<const int64_t *>(ws(p, p.ws_tap_twoff));
-        ta.tap_idx = reinterpret_cast<const int2 *>(ws(p, p.ws_tap_idx));
-        ta.out = static_cast<float2 *>(d_tap);
-        ta.c0 = b.c0;
-        ta.n_chan_block = b.c1 - b.c0;
-        ta.t0 = (int)t0;
-        ta.nt = nt;
-        ta.t_block = p.t_block;
-        ta.n_chan = p.n_chan;
-        ta.n_tap = p.n_tap;
-        ta.P = p.n_pol;
-        HIP_TRY(moff::launch_tap(ta, rs), "tap");
+    }
+    return MOFF_OK;
+  }
+  // fixed exchange buffer: each plan block is cut into channel runs whose one sample fits it, and each run takes
+  // as many samples per launch block as fit (at most the plan's time block)
+  for (const moff::Block &b : p.blocks) {
+    if (b.c0 < c_lo || b.c1 > c_hi) continue;
+    const size_t per_cs = (size_t)p.n_pol * b.n * b.n * 8;   // one channel-sample of row-transformed grids
+    const int c_run = (int)std::min<size_t>((size_t)(b.c1 - b.c0), ex->bytes / per_cs);
+    if (c_run < 1) return set_err(MOFF_E_UNSUPPORTED, "one channel-sample needs more than the exchange buffer");
+    for (int c0 = b.c0; c0 < b.c1; c0 += c_run) {
+      const moff::Block sb{c0, std::min(b.c1, c0 + c_run), b.n};
+      const int tblk = (int)std::min<size_t>((size_t)p.t_block, ex->bytes / (per_cs * (size_t)(sb.c1 - sb.c0)));
+      for (int64_t t0 = 0; t0 < n_t; t0 += tblk) {
+        moff_status r = one_block(sb, t0, (int)std::min<int64_t>(tblk, n_t - t0), tblk);
+        if (r) return r;
       }
-      if (dual) {
-        HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(p.ev_rows[slot]), rs), "row event");
-        HIP_TRY(hipStreamWaitEvent(st, static_cast<hipEvent_t>(p.ev_rows[slot]), 0), "row wait");
-      }
-      const int W = p.chans[b.c0].cols;
-      ca.c0 = b.c0;
-      ca.t0 = (int)t0;
-      ca.nt = nt;
-      ca.tw = a.tw;
-      const int grid = moff::cols_xcd_grid(b, b.n / W);
-      ca.n_chan_block = b.c1 - b.c0;
-      {
-        ProfScope ps(p, st, 1, cs);
-        if (split)
-          HIP_TRY(moff::launch_cols_mfma(bf16, p.acc_mode, ca, mtab, grid, st), "column pass");
-        else
-          HIP_TRY(moff::launch_cols(b.n, p.n_pol, W, moff::COL_MODE_FUSED, p.acc_mode, ca, grid, 1,
-                                    moff::cols_lds_bytes(b.n, p.n_pol, W), st),
-                  "column pass");
-        HIP_TRY(ps.done(), "profile event");
-      }
-      if (dual) HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(p.ev_cols[slot]), st), "column event");
-      ++k;
     }
   }
   return MOFF_OK;
@@ -413,6 +447,9 @@ moff_status moff_bind(moff_plan_t plan, void *d_ws, size_t bytes, void *stream) 
   if (!p.bands.empty())
     HIP_TRY(hipMemcpyAsync(ws(p, p.ws_bands), p.bands.data(), p.bands.size() * sizeof(moff::Band),
                            hipMemcpyHostToDevice, st), "upload bands");
+  if (!p.fft_bands.empty())
+    HIP_TRY(hipMemcpyAsync(ws(p, p.ws_fft_bands), p.fft_bands.data(), p.fft_bands.size() * sizeof(moff::Band),
+                           hipMemcpyHostToDevice, st), "upload full-grid bands");
   HIP_TRY(hipMemcpyAsync(ws(p, p.ws_chans), p.chans.data(), p.chans.size() * sizeof(moff::Chan),
                          hipMemcpyHostToDevice, st), "upload channels");
   if (p.n_groups) {
@@ -501,7 +538,10 @@ moff_status moff_fft(moff_plan_t plan, void *d_grid, int64_t n_t, void *stream) 
   if (n_t == 0) return ok();
   if (n_t > INT32_MAX / 2) return set_err(MOFF_E_INVALID, "n_t too large for one call");
   hipStream_t st = static_cast<hipStream_t>(stream);
+  // every row and column is transformed (the full-grid bands, no footprint row range): the grids may hold data
+  // anywhere
   moff::RowArgs a = row_args(p, nullptr);
+  a.bands = reinterpret_cast<const moff::Band *>(ws(p, p.ws_fft_bands));
   a.io = static_cast<float2 *>(d_grid);
   a.t0 = 0;
   a.nt = (int)n_t;
@@ -513,9 +553,10 @@ moff_status moff_fft(moff_plan_t plan, void *d_grid, int64_t n_t, void *stream) 
   ca.nt = (int)n_t;
   ca.t_block = 0;
   ca.sample_stride = (int64_t)p.n_pol * p.pix_total;
+  ca.full_rows = 1;
   for (const moff::Block &b : p.blocks) {
-    a.band_begin = band_begin(p, b);
-    a.n_bands = band_count(p, b);
+    a.band_begin = p.fft_band_first[b.c0];
+    a.n_bands = p.fft_band_first[b.c1] - p.fft_band_first[b.c0];
     a.c0 = b.c0;
     a.tw = d_tw(p, b.n);
     const int tgroups = (int)((n_t + p.t_group - 1) / p.t_group);

@@ -60,6 +60,10 @@ struct Plan {
   std::vector<Chan> chans;
   std::vector<int32_t> origin;          // [C][A][2] (j0, i0)
   std::vector<Band> bands;
+  // staged 2-D FFT (moff_fft): bands covering every row of each channel's grid (no tap groups), channel c's
+  // at fft_band_first[c] .. fft_band_first[c + 1] - 1
+  std::vector<Band> fft_bands;
+  std::vector<int32_t> fft_band_first;
   std::vector<int32_t> band_ptr;        // [n_bands + 1] into band_ant
   std::vector<int32_t> band_ant;        // antennas of each band, ascending
   int32_t max_band_ants = 0;           // largest band antenna list of the sizes with a voltage table (LDS size)
@@ -90,6 +94,7 @@ struct Plan {
   std::vector<int32_t> tw_sizes;        // distinct n values in the order of the tables
   std::vector<size_t> tw_off;           // byte offset of each table
   size_t ws_bands = 0;                  // Band array (device copy)
+  size_t ws_fft_bands = 0;              // full-grid bands of the staged FFT (device copy)
   size_t ws_chans = 0;                  // Chan array (device copy)
   size_t ws_meta = 0, ws_kidx = 0, ws_gchan = 0, ws_wk = 0;  // tap groups; packed kernels float2 [G][64][planes]
   size_t ws_band_ant = 0;               // band antenna lists (int32)

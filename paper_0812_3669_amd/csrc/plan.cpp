@@ -376,6 +376,24 @@ moff_status build_plan(const moff_plan_desc &d, Plan &p, std::string *err) {
     cb = ChanBuild();   // release the channel's copy
   });
   if ((int64_t)p.bands.size() > INT32_MAX / 2) return fail(err, MOFF_E_UNSUPPORTED, "too many bands");
+  // full-grid bands of the staged 2-D FFT: every row, whatever the footprints touch
+  p.fft_bands.clear();
+  p.fft_band_first.assign((size_t)C + 1, 0);
+  for (int c = 0; c < C; ++c) {
+    const Chan &ch = p.chans[c];
+    p.fft_band_first[(size_t)c] = (int32_t)p.fft_bands.size();
+    for (int row0 = 0; row0 < ch.n; row0 += ch.band_rows) {
+      Band bd{};
+      bd.chan = c;
+      bd.row0 = row0;
+      bd.rows = std::min(ch.band_rows, ch.n - row0);
+      bd.r_lo = row0;
+      bd.r_hi = row0 + bd.rows - 1;
+      p.fft_bands.push_back(bd);
+    }
+  }
+  p.fft_band_first[(size_t)C] = (int32_t)p.fft_bands.size();
+  if ((int64_t)p.fft_bands.size() > INT32_MAX / 2) return fail(err, MOFF_E_UNSUPPORTED, "too many bands");
 
   // ---- workspace layout (launch blocks and the row-transform buffer last) -------------------------------
   size_t off = 0;
@@ -391,6 +409,8 @@ moff_status build_plan(const moff_plan_desc &d, Plan &p, std::string *err) {
   }
   p.ws_bands = off;
   off = align256(off + p.bands.size() * sizeof(Band));
+  p.ws_fft_bands = off;
+  off = align256(off + p.fft_bands.size() * sizeof(Band));
   p.ws_chans = off;
   off = align256(off + p.chans.size() * sizeof(Chan));
   p.ws_meta = off;

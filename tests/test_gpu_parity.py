@@ -98,6 +98,27 @@ def test_staged_fft_every_size(n):
     assert err < 2e-6, err
 
 
+@pytest.mark.parametrize("n", [64, 192, 256, 384])
+def test_staged_fft_full_random_grid(n):
+    """moff_fft on random grids with data in every cell (rows and columns no footprint touches included)
+    against the oracle's direct DFT: the staged transform covers the whole grid, not the footprint rows only."""
+    cfg = _small(n, C=2, A=12, T=3, disk=0.3 * n, seed=n + 1)
+    geo, kern, volts, plan = _setup(cfg)
+    rng = np.random.default_rng(n)
+    G = (rng.standard_normal((cfg.n_time, 2 * plan.pix_total)) +
+         1j * rng.standard_normal((cfg.n_time, 2 * plan.pix_total))).astype(np.complex64)
+    buf = torch.from_numpy(np.ascontiguousarray(G.reshape(-1))).to(DEV)
+    plan.fft(buf, cfg.n_time)
+    ef = plan.split_grids(buf, cfg.n_time)
+    for c in range(cfg.n_chan):
+        o = 2 * plan.pix_off[c]
+        g = G[:, o:o + 2 * n * n].reshape(cfg.n_time, 2, n, n).astype(np.complex128)
+        ref = ora.efield_image(g)
+        got = np.fft.fftshift(ef[c].cpu().numpy(), axes=(-2, -1))
+        err = np.abs(got - ref).max() / np.abs(ref).max()
+        assert err < 2e-6, (c, err)
+
+
 def test_staged_accumulate_and_readout():
     n = 64
     cfg = _small(n, C=2, A=20, T=6)
@@ -231,6 +252,50 @@ def test_deterministic_and_split_integration():
     torch.cuda.synchronize()
     assert torch.equal(a1, a2)
     assert torch.equal(a1, a3)
+
+
+def _edge_setup(n, K, T, A_inner=24, seed=0):
+    """One channel at f = c (one metre = one wavelength, cell 1): eight antennas whose footprints touch grid
+    rows and columns 0 and n - 1 (the four corners and the four edge midpoints), plus random interior antennas;
+    random complex kernels and random int8 voltages."""
+    rng = np.random.default_rng(seed)
+    lo, hi, mid = K // 2 - 1 + 0.3, n - 1 - K // 2 + 0.6, n / 2 + 0.45    # floor(X) = K/2 - 1, n - 1 - K/2
+    edge = [(x, y) for x in (lo, mid, hi) for y in (lo, mid, hi) if (x, y) != (mid, mid)]
+    inner = rng.uniform(K + 2, n - K - 2, size=(A_inner, 2))
+    XY = np.concatenate([np.array(edge), inner])
+    xy = XY - n / 2                                                        # metres east, north
+    geo = synth.Geometry(xy, np.array([configs.C_LIGHT]), np.array([n], dtype=np.int32), 1.0, K)
+    origin = ora.footprint_origin(xy, configs.C_LIGHT, 1.0, n, K)
+    assert origin[:, 0].min() == 0 and origin[:, 1].min() == 0
+    assert origin[:, 0].max() + K == n and origin[:, 1].max() + K == n
+    A = xy.shape[0]
+    kern = (rng.standard_normal((1, A, 2, K, K)) + 1j * rng.standard_normal((1, A, 2, K, K))).astype(np.complex64)
+    volts = rng.integers(-127, 128, size=(T, 1, A, 2, 2)).astype(np.int8)
+    cfg = configs.scaled(configs.PLAIN, n_ant=A, n_chan=1, ksize=K, grid_n=n, n_time=T)
+    return cfg, geo, kern, volts
+
+
+@pytest.mark.parametrize("n,K,fft", [(256, 4, api.FFT_FP32), (384, 6, api.FFT_FP32), (256, 4, api.FFT_SPLIT_FP16),
+                                     (256, 4, api.FFT_SPLIT_BF16)])
+def test_footprints_on_grid_edges(n, K, fft):
+    """Footprints on grid rows and columns 0 and n - 1: the first and last bands, the row-range masks of the
+    column pass and the grid borders of the scatter; 40 samples (a row group of 32 and a ragged one)."""
+    cfg, geo, kern, volts = _edge_setup(n, K, T=40, seed=n + fft)
+    plan = api.plan_for(cfg, geo, fft_mode=fft).bind(DEV)
+    plan.set_kernels(torch.from_numpy(kern).to(DEV))
+    imgs, _ = _run_fused(plan, volts)
+    ref = ora.image(volts, kern, geo.ant_xy_m, geo.freqs_hz, geo.grid_n, cfg.cell_lambda)
+    _check_images(imgs, ref, label=f"edges n={n} fft={fft}", report=True)
+    if fft == api.FFT_FP32:
+        g = plan.grid(torch.from_numpy(volts).to(DEV))
+        grids = plan.split_grids(g, cfg.n_time)[0].cpu().numpy()
+        origin = ora.footprint_origin(geo.ant_xy_m, geo.freqs_hz[0], 1.0, n, K)
+        e = ora.unpack(volts)
+        for p in range(2):
+            r = ora.grid_many(e[:, 0, :, p], kern[0, :, p], origin, n)
+            assert np.abs(grids[:, p] - r).max() <= 1e-6 * np.abs(r).max(), p
+            assert np.abs(r[:, 0, :]).max() > 0 and np.abs(r[:, n - 1, :]).max() > 0
+            assert np.abs(r[:, :, 0]).max() > 0 and np.abs(r[:, :, n - 1]).max() > 0
 
 
 def test_hermitian_products_and_positivity():

@@ -161,6 +161,69 @@ def test_point_source_mirrored_sign_fails():
 
 
 # ---------------------------------------------------------------------------------------------------------
+# 3b. int8 voltages (Eq. Ea and its footnote: the A/D quantisation folded into the noise term)
+# ---------------------------------------------------------------------------------------------------------
+def _quantised_quarter_source(n, dq, amps, seed=3, A=12):
+    """A lone source at a quarter-grid pixel offset seen by delta-kernel antennas on integer cells: every
+    antenna's phase exp(-2 pi i (x l + y m)) is a power of i, so quantising s_t times it is exact per
+    component (one of re, im is 0, the other +-Q(s_t)), with Q(s) = clip(rint(s), -127, 127)."""
+    rng = np.random.default_rng(seed)
+    K = 4
+    cells = rng.choice(np.arange(6, n - 6), size=(A, 2))
+    ant_xy = np.stack([cells[:, 1] - n / 2, cells[:, 0] - n / 2], axis=1).astype(np.float64)
+    qs, ps = n // 2 + dq[0], n // 2 + dq[1]
+    l_s, m_s = (ps - n / 2) / n, (qs - n / 2) / n
+    ph = np.exp(-2j * np.pi * (ant_xy[:, 0] * l_s + ant_xy[:, 1] * m_s))          # powers of i
+    x = np.asarray(amps, dtype=np.float64)[:, None] * ph[None, :]                # [T, A]
+    q = np.zeros(x.shape + (2,), dtype=np.int8)
+    q[..., 0] = np.clip(np.rint(x.real), -127, 127).astype(np.int8)
+    q[..., 1] = np.clip(np.rint(x.imag), -127, 127).astype(np.int8)
+    kern = np.zeros((1, A, 1, K, K), dtype=np.complex64)
+    kern[0, :, 0, K // 2 - 1, K // 2 - 1] = 1.0
+    return q[:, None, :, None, :], kern, ant_xy, (qs, ps)
+
+
+@pytest.mark.parametrize("dq", [(0, 8), (8, -8), (-8, 0)])
+def test_int8_quarter_pixel_source_closed_form(dq):
+    """int8 (re, im) pairs read as re + i im: the quantised lone source images at its own pixel with the
+    closed-form power sum_t (A Q(s_t))^2 (rounding half to even and the clip at 127 included).  Reading the
+    pair as im + i re, or conjugating it, mirrors the image and moves the peak off the source pixel."""
+    n = 32
+    amps = [100.4, 37.5, 38.5, -64.49, 300.0, 127.6]          # rint: 100, 38, 38, -64; clipped: 127, 127
+    volts, kern, ant_xy, (qs, ps) = _quantised_quarter_source(n, dq, amps)
+    img = ora.image(volts, kern, ant_xy, [configs.C_LIGHT], [n], 1.0)[0][0].real
+    A = ant_xy.shape[0]
+    q_amp = np.clip(np.rint(np.asarray(amps)), -127, 127)
+    assert list(q_amp) == [100, 38, 38, -64, 127, 127]
+    expect = float(np.sum((A * q_amp) ** 2))
+    assert np.unravel_index(np.argmax(img), img.shape) == (qs, ps)
+    assert img[qs, ps] == expect                                  # integer arithmetic, exact in FP64
+    swapped = volts[..., ::-1].copy()
+    img_sw = ora.image(swapped, kern, ant_xy, [configs.C_LIGHT], [n], 1.0)[0][0].real
+    conj = volts.copy()
+    conj[..., 1] = -conj[..., 1]
+    img_cj = ora.image(conj, kern, ant_xy, [configs.C_LIGHT], [n], 1.0)[0][0].real
+    for wrong in (img_sw, img_cj):
+        assert wrong[qs, ps] < 0.5 * expect
+        assert np.unravel_index(np.argmax(wrong), wrong.shape) == ((n - qs) % n, (n - ps) % n)
+
+
+def test_int8_equals_the_same_values_as_complex64():
+    """The int8 branch of the unpack step gives exactly the complex values re + i im: an image from int8
+    voltages equals, bit for bit, the image from those values stored as complex64 (including -128)."""
+    cfg, geo, kern, volts = _small(2, A=18, T=5, seed=12)
+    assert volts.dtype == np.int8
+    volts = volts.copy()
+    volts[0, 0, 0, 0] = (-128, 127)
+    volts[1, 0, 3, 1] = (5, -128)
+    c64 = (volts[..., 0].astype(np.float32) + 1j * volts[..., 1].astype(np.float32)).astype(np.complex64)
+    assert np.array_equal(ora.unpack(volts), c64.astype(np.complex128))
+    a = ora.image(volts, kern, geo.ant_xy_m, geo.freqs_hz, geo.grid_n, cfg.cell_lambda)[0]
+    b = ora.image(c64, kern, geo.ant_xy_m, geo.freqs_hz, geo.grid_n, cfg.cell_lambda)[0]
+    assert np.array_equal(a, b)
+
+
+# ---------------------------------------------------------------------------------------------------------
 # 4. Reduction to the direct-imaging correlator and numpy's inverse FFT
 # ---------------------------------------------------------------------------------------------------------
 def test_delta_kernels_reduce_to_ifft2():
