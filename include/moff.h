@@ -177,6 +177,20 @@ moff_status moff_autotune(moff_plan_t plan, const void *d_volt, int64_t n_t, voi
  * rebinding drops the cached graphs.  The buffers' contents may change between calls; their addresses may not. */
 moff_status moff_correlate_graph(moff_plan_t plan, const void *d_volt, int64_t n_t, void *d_acc, void *stream);
 
+/* For callers that cannot allocate device memory when they correlate (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): moff_correlate with the row-transformed grids passing through a fixed
+ * buffer that the library owns, MOFF_NOALLOC_EXCHANGE_BYTES on each GPU it runs on (a device array held from the
+ * first call on that GPU until the process ends), instead of the workspace's exchange region.  It calls no
+ * hipMalloc or hipFree and allocates nothing else.  Launch blocks are cut (channels, then samples) so that one
+ * block's exchange fits the buffer, which makes it slower than moff_correlate; results equal moff_correlate's up
+ * to FP32 summation order (the accumulator is updated per shorter block).  Two-pass form whatever the pipeline
+ * setting.  MOFF_E_UNSUPPORTED if one channel-sample of the plan needs more than the buffer (P n^2 x 8 bytes; every
+ * supported grid size fits).  Every call on one GPU shares the buffer, which keeps the last call's contents (each
+ * call writes what it reads): calls that overlap on one GPU (concurrent streams, other plans, other host
+ * threads) race. */
+#define MOFF_NOALLOC_EXCHANGE_BYTES (64u << 20)
+moff_status moff_correlate_noalloc(moff_plan_t plan, const void *d_volt, int64_t n_t, void *d_acc, void *stream);
+
 /* How the fused path (moff_correlate, moff_correlate_graph) moves the row-transformed grids to the column pass
  * -- the all-to-all of a 2-D FFT too large for one compute unit, which the paper's modular design does between
  * spatial modules (Section 5).  MOFF_PIPELINE_TWO_PASS (default): a row-pass kernel writes them for a launch

@@ -61,6 +61,7 @@ _SIGS = {
     "moff_autotune": ([_P, _P, C.c_int64, _P, _P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                        C.POINTER(C.c_double)], C.c_int),
     "moff_correlate_graph": ([_P, _P, C.c_int64, _P, _P], C.c_int),
+    "moff_correlate_noalloc": ([_P, _P, C.c_int64, _P, _P], C.c_int),
     "moff_profile": ([_P, C.c_int32], C.c_int),
     "moff_profile_read": ([_P, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_int64)],
                           C.c_int),

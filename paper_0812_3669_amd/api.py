@@ -216,6 +216,15 @@ class Plan:
         _check(self.lib.moff_correlate_graph(self._h, _ptr(volts), n_t, _ptr(acc), _stream_handle(stream)),
                "moff_correlate_graph")
 
+    def correlate_noalloc(self, volts, acc, n_t: Optional[int] = None, stream=None):
+        """Same as correlate, with the row-transformed grids in the library's fixed exchange buffer (allocates no
+        device memory; for callers that cannot)."""
+        n_t = volts.shape[0] if n_t is None else n_t
+        self._check_volts(volts, n_t)
+        self._check_acc(acc)
+        _check(self.lib.moff_correlate_noalloc(self._h, _ptr(volts), n_t, _ptr(acc), _stream_handle(stream)),
+               "moff_correlate_noalloc")
+
     # ---- E-field taps and feedback calibration ---------------------------------------------------------------------
     def set_taps(self, pix, stream=None):
         """pix int [C, n_tap, 2] (or [n_tap, 2] for every channel): centred (row, col) pixels of each channel."""

@@ -328,6 +328,11 @@ hipError_t launch_mfma_table(uint16_t *tab, int bf16, hipStream_t st);
 hipError_t launch_rows_mfma(int bf16, const RowArgs &a, const uint16_t *table, int grid, hipStream_t st);
 hipError_t launch_cols_mfma(int bf16, int accm, const ColArgs &a, const uint16_t *table, int grid, hipStream_t st);
 
+// Exchange buffer of the no-alloc entry point (kernels_noalloc.hip): its device address on the current device
+// (looked up once per device) and its size.
+constexpr size_t kNoallocExchangeBytes = (size_t)MOFF_NOALLOC_EXCHANGE_BYTES;
+hipError_t noalloc_exchange(void **ptr, size_t *bytes);
+
 // Issue-rate probes (kernels_probe.hip): kind 0 FP32 vector FMAs, kind 1 FP16 matrix-core instructions.
 hipError_t launch_probe(int kind, int blocks, int iters, float *out, hipStream_t st);
 

@@ -190,7 +190,7 @@ moff_status enqueue_stream(moff::Plan &p, const void *d_volt, int64_t n_t, void 
 }
 
 // Where the two-pass form puts the row-transformed grids of a launch block: by default the workspace's
-// exchange region (p.t_block samples of one of the plan's channel blocks); a caller can pass instead a
+// exchange region (p.t_block samples of one of the plan's channel blocks); the no-alloc entry point passes a
 // fixed buffer of `bytes`, and the launch blocks are cut (channels, then samples) so that one fits it.
 struct Exchange {
   float2 *base;
@@ -605,6 +605,29 @@ moff_status moff_correlate(moff_plan_t plan, const void *d_volt, int64_t n_t, vo
   if (n_t == 0) return ok();
   if (n_t > INT32_MAX / 2) return set_err(MOFF_E_INVALID, "n_t too large for one call");
   s = enqueue_correlate(p, d_volt, n_t, d_acc, static_cast<hipStream_t>(stream));
+  return s ? s : ok();
+}
+
+moff_status moff_correlate_noalloc(moff_plan_t plan, const void *d_volt, int64_t n_t, void *d_acc, void *stream) {
+  if (!plan) return set_err(MOFF_E_INVALID, "null plan");
+  if (n_t < 0) return set_err(MOFF_E_INVALID, "n_t must be >= 0");
+  if (n_t > 0 && (!d_volt || !d_acc)) return set_err(MOFF_E_INVALID, "null buffer");
+  moff::Plan &p = plan->p;
+  moff_status s = need_bound(p, true);
+  if (s) return s;
+  // the largest channel-sample of row-transformed grids must fit the library's buffer
+  for (const moff::Chan &c : p.chans)
+    if ((size_t)p.n_pol * c.n * c.n * 8 > moff::kNoallocExchangeBytes)
+      return set_err(MOFF_E_UNSUPPORTED, "a channel-sample of this plan needs more than the " +
+                                             std::to_string(moff::kNoallocExchangeBytes >> 20) +
+                                             " MiB exchange buffer of moff_correlate_noalloc");
+  if (n_t == 0) return ok();
+  if (n_t > INT32_MAX / 2) return set_err(MOFF_E_INVALID, "n_t too large for one call");
+  Exchange ex{};
+  void *buf = nullptr;
+  HIP_TRY(moff::noalloc_exchange(&buf, &ex.bytes), "exchange buffer address");
+  ex.base = static_cast<float2 *>(buf);
+  s = enqueue_two_pass(p, d_volt, n_t, d_acc, static_cast<hipStream_t>(stream), 0, p.n_chan, nullptr, &ex);
   return s ? s : ok();
 }
 
