@@ -181,7 +181,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--acc", choices=["fp32", "fp64"], default="fp32")
-    ap.add_argument("--fft", choices=["fp32", "split_fp16", "split_bf16"], default="fp32",
+    ap.add_argument("--fft", choices=["fp32", "split_fp16", "split_bf16", "gemm_fp16"], default="fp32",
                     help="transform arithmetic: plain FP32 (VALU) or split-precision matrix-core DFT-GEMMs")
     ap.add_argument("--time", type=int, default=0, help="samples per step (default: the full 16384)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -264,7 +264,8 @@ def main():
     kern_np = synth.kernels(geo, g, cfg.n_pol)
     volts = synth.DeviceVoltages(cfg, geo, g, sk, dev, chunk=64).all(T)
     acc_mode = api.ACC_FP64_COMP if args.acc == "fp64" else api.ACC_FP32
-    fft_mode = {"fp32": api.FFT_FP32, "split_fp16": api.FFT_SPLIT_FP16, "split_bf16": api.FFT_SPLIT_BF16}[args.fft]
+    fft_mode = {"fp32": api.FFT_FP32, "split_fp16": api.FFT_SPLIT_FP16, "split_bf16": api.FFT_SPLIT_BF16,
+                "gemm_fp16": api.FFT_GEMM_FP16}[args.fft]
     plan = api.plan_for(cfg, geo, acc_mode=acc_mode, fft_mode=fft_mode)
     # room for every shape the autotuner tries, up to 16384 channel-samples per launch
     room = max(plan.workspace_bytes_for(tb, cpb) for tb in (8, 16, 32, 64, 128, 256)
@@ -325,7 +326,7 @@ def main():
             return cfg.flops_per_cs(n)                       # streaming form: the whole path in one kernel
         return 8.0 * A * P * K * K + fft_half if kind == 0 else fft_half + 16.0 * n * n
 
-    names = {0: "k_rows", 1: "k_cols", 2: "k_stream"}
+    names = {0: "k_rowgemm" if args.fft == "gemm_fp16" else "k_rows", 1: "k_cols", 2: "k_stream"}
     split = args.fft in SPLIT_PRODUCTS
     if split:
         # the matrix-core passes transform every row of the touched bands and every column (256^2, two pols)
@@ -372,7 +373,8 @@ def main():
         "metric": metric + ("plain FP32 path" if args.fft == "fp32" else f"{args.fft} matrix-core transform"),
         "value": value, "unit": "channel-samples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": {"fp32": "f32", "split_fp16": "f16x2->f32", "split_bf16": "bf16x3->f32"}[args.fft],
+        "dtype": {"fp32": "f32", "split_fp16": "f16x2->f32", "split_bf16": "bf16x3->f32",
+                  "gemm_fp16": "f16x2->f32 (row GEMM) + f32"}[args.fft],
         "data": "synthetic (seeded point sources + noise, int8 voltages)",
         "config": {"workload": workload,
                    "channel_samples_per_step": cs, "accumulator": args.acc,

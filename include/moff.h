@@ -63,7 +63,17 @@ typedef enum {
   MOFF_E_STATE = 5        /* call out of order: not bound, kernels not set */
 } moff_status;
 
-typedef enum { MOFF_FFT_FP32 = 0, MOFF_FFT_SPLIT_FP16 = 1, MOFF_FFT_SPLIT_BF16 = 2 } moff_fft_mode;
+/* Arithmetic of gridding and the spatial transform.
+ *   FP32: scatter gridding in LDS and radix-2/3/4/5/8/16 FFT stages on the vector units.
+ *   SPLIT_FP16 / SPLIT_BF16 (256^2 grids, two pols): FP32 gridding, both FFT passes as radix-16 DFT-GEMMs on the
+ *     matrix cores with split 16-bit products.
+ *   GEMM_FP16: gridding and the row half of the transform together as one matrix-core GEMM over time samples,
+ *     H[t][j][k] = sum over the antennas a whose footprint covers grid row j of E[t][a] Phi_a[k], with
+ *     Phi_a[k] = w^(i0_a k) sum_x W_a[j - j0_a][x] w^(x k) (w = e^(2 pi i / n)): the int8 voltages are exact in FP16,
+ *     Phi is formed in FP32 from the kernel and split into FP16 hi + lo terms (two products, FP32 accumulation);
+ *     the column half and the products are the FP32 column pass.  Any supported grid size, diagonal kernels, int8
+ *     voltages. */
+typedef enum { MOFF_FFT_FP32 = 0, MOFF_FFT_SPLIT_FP16 = 1, MOFF_FFT_SPLIT_BF16 = 2, MOFF_FFT_GEMM_FP16 = 3 } moff_fft_mode;
 typedef enum { MOFF_ACC_FP32 = 0, MOFF_ACC_FP64_COMP = 1 } moff_acc_mode;
 typedef enum { MOFF_VOLT_INT8 = 0, MOFF_VOLT_C64 = 1 } moff_volt_format;
 /* Diagonal kernels: the X grid receives only X voltages (through K_{a,X}) and the Y grid only Y voltages.

@@ -10,7 +10,7 @@ LIB_PATH = os.path.join(PKG, "libmoff.so")
 HEADER = os.path.join(os.path.dirname(PKG), "include", "moff.h")
 
 MOFF_OK, MOFF_E_INVALID, MOFF_E_BUDGET, MOFF_E_DEVICE, MOFF_E_UNSUPPORTED, MOFF_E_STATE = range(6)
-FFT_FP32, FFT_SPLIT_FP16, FFT_SPLIT_BF16 = range(3)
+FFT_FP32, FFT_SPLIT_FP16, FFT_SPLIT_BF16, FFT_GEMM_FP16 = range(4)
 ACC_FP32, ACC_FP64_COMP = range(2)
 VOLT_INT8, VOLT_C64 = range(2)
 KERNEL_DIAG, KERNEL_JONES = range(2)

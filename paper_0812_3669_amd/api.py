@@ -15,7 +15,7 @@ from typing import List, Optional, Sequence
 import numpy as np
 
 from . import _lib
-from ._lib import (ACC_FP32, ACC_FP64_COMP, FFT_FP32, FFT_SPLIT_BF16, FFT_SPLIT_FP16,  # noqa: F401
+from ._lib import (ACC_FP32, ACC_FP64_COMP, FFT_FP32, FFT_GEMM_FP16, FFT_SPLIT_BF16, FFT_SPLIT_FP16,  # noqa: F401
                    KERNEL_DIAG, KERNEL_JONES, PIPELINE_STREAM, PIPELINE_TWO_PASS, VOLT_C64, VOLT_INT8)
 
 

@@ -17,7 +17,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libmoff.so")
 SOURCES = ["plan.cpp", "moff_api.cpp", "kernels.hip", "kernels_mfma.hip", "kernels_cal.hip", "kernels_probe.hip",
-           "kernels_noalloc.hip"]
+           "kernels_noalloc.hip", "kernels_rowgemm.hip"]
 ARCH = os.environ.get("MOFF_OFFLOAD_ARCH", "gfx950")
 
 

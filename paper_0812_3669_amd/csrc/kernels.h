@@ -328,6 +328,24 @@ hipError_t launch_mfma_table(uint16_t *tab, int bf16, hipStream_t st);
 hipError_t launch_rows_mfma(int bf16, const RowArgs &a, const uint16_t *table, int grid, hipStream_t st);
 hipError_t launch_cols_mfma(int bf16, int accm, const ColArgs &a, const uint16_t *table, int grid, hipStream_t st);
 
+// Matrix-core row pass (kernels_rowgemm.hip): gridding and row transform as one split-FP16 GEMM over time samples.
+struct RgArgs {
+  const Chan *chans;
+  const int32_t *rows;       // [touched rows][2]: first entry, antenna count (channel c's row jmin at chans[c].rg_first)
+  const uint32_t *ents;      // antenna | (row - j0) << 16 | i0 << 20
+  const float2 *rk;          // kernels [C][A][P][K][K], phases folded
+  const float2 *tw;          // w^m, m < n
+  const void *volt;          // int8 [T][C][A][P][2]
+  float2 *io;                // H of the launch block (column-group tiles, as the FP32 row pass writes it)
+  int c0, n_chan_block, t0, nt, t_block, n_chan, n_ant, K, P;
+  int tt;                    // samples per time tile (multiple of 16, <= 128)
+  int slots;                 // antenna slots of the LDS tables (the longest row list, rounded up to 16)
+};
+int rowgemm_grid(const Plan &p, const Block &b, int nt);
+hipError_t launch_rowgemm(int n, const RgArgs &a, int grid, hipStream_t st);
+hipError_t launch_rg_twiddle(float2 *tw, int n, hipStream_t st);
+hipError_t launch_pack_rk(const float2 *kern, const float2 *phase, float2 *rk, int64_t total, int KK, hipStream_t st);
+
 // Exchange buffer of the no-alloc entry point (kernels_noalloc.hip): its device address on the current device
 // (looked up once per device) and its size.
 constexpr size_t kNoallocExchangeBytes = (size_t)MOFF_NOALLOC_EXCHANGE_BYTES;

@@ -54,6 +54,12 @@ const float2 *d_tw(const moff::Plan &p, int n) {
   return nullptr;
 }
 
+const float2 *d_rgtw(const moff::Plan &p, int n) {
+  for (size_t i = 0; i < p.tw_sizes.size() && i < p.rgtw_off.size(); ++i)
+    if (p.tw_sizes[i] == n) return reinterpret_cast<const float2 *>(ws(p, p.rgtw_off[i]));
+  return nullptr;
+}
+
 moff_status need_bound(const moff::Plan &p, bool kernels) {
   if (!p.bound) return set_err(MOFF_E_STATE, "plan is not bound to a workspace (moff_bind)");
   if (kernels && !p.kernels_set) return set_err(MOFF_E_STATE, "kernels are not set (moff_set_kernels)");
@@ -217,7 +223,7 @@ moff_status enqueue_two_pass(moff::Plan &p, const void *d_volt, int64_t n_t, voi
     HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(p.ev_fork), st), "fork event");
     HIP_TRY(hipStreamWaitEvent(rs, static_cast<hipEvent_t>(p.ev_fork), 0), "fork wait");
   }
-  const bool split = p.fft_mode != MOFF_FFT_FP32;
+  const bool split = p.split_mfma();
   const int bf16 = p.fft_mode == MOFF_FFT_SPLIT_BF16;
   const uint16_t *mtab = reinterpret_cast<const uint16_t *>(ws(p, p.ws_mfma));
   int64_t k = 0;
@@ -243,7 +249,28 @@ moff_status enqueue_two_pass(moff::Plan &p, const void *d_volt, int64_t n_t, voi
     {
       ProfScope ps(p, rs, 0, cs);
       const int rgrid = moff::rows_xcd_grid(p, b, tgroups);
-      if (split)
+      if (p.gemm()) {
+        moff::RgArgs g{};
+        g.chans = d_chans(p);
+        g.rows = reinterpret_cast<const int32_t *>(ws(p, p.ws_rg_rows));
+        g.ents = reinterpret_cast<const uint32_t *>(ws(p, p.ws_rg_ents));
+        g.rk = reinterpret_cast<const float2 *>(ws(p, p.ws_rk));
+        g.tw = d_rgtw(p, b.n);
+        g.volt = d_volt;
+        g.io = H;
+        g.c0 = b.c0;
+        g.n_chan_block = b.c1 - b.c0;
+        g.t0 = (int)t0;
+        g.nt = nt;
+        g.t_block = tblk;
+        g.n_chan = p.n_chan;
+        g.n_ant = p.n_ant;
+        g.K = p.ksize;
+        g.P = p.n_pol;
+        g.tt = p.rg_tt;
+        g.slots = (p.rg_max_ants + 15) / 16 * 16;
+        HIP_TRY(moff::launch_rowgemm(b.n, g, moff::rowgemm_grid(p, b, nt), rs), "row pass");
+      } else if (split)
         HIP_TRY(moff::launch_rows_mfma(bf16, a, mtab, rgrid, rs), "row pass");
       else
         HIP_TRY(moff::launch_rows(b.n, p.n_pol, moff::ROW_MODE_FUSED, jones, a, rgrid, lds, rs), "row pass");
@@ -466,10 +493,21 @@ moff_status moff_bind(moff_plan_t plan, void *d_ws, size_t bytes, void *stream) 
             "upload band antenna lists");
   for (size_t i = 0; i < p.tw_sizes.size(); ++i)
     HIP_TRY(moff::launch_twiddle(reinterpret_cast<float2 *>(ws(p, p.tw_off[i])), p.tw_sizes[i], st), "twiddles");
-  if (p.fft_mode != MOFF_FFT_FP32)
+  if (p.split_mfma())
     HIP_TRY(moff::launch_mfma_table(reinterpret_cast<uint16_t *>(ws(p, p.ws_mfma)),
                                     p.fft_mode == MOFF_FFT_SPLIT_BF16, st),
             "split-transform matrices");
+  if (p.gemm()) {
+    if (!p.rg_rows.empty())
+      HIP_TRY(hipMemcpyAsync(ws(p, p.ws_rg_rows), p.rg_rows.data(), p.rg_rows.size() * 4, hipMemcpyHostToDevice, st),
+              "upload row table");
+    if (!p.rg_ents.empty())
+      HIP_TRY(hipMemcpyAsync(ws(p, p.ws_rg_ents), p.rg_ents.data(), p.rg_ents.size() * 4, hipMemcpyHostToDevice, st),
+              "upload row entries");
+    for (size_t i = 0; i < p.tw_sizes.size(); ++i)
+      HIP_TRY(moff::launch_rg_twiddle(reinterpret_cast<float2 *>(ws(p, p.rgtw_off[i])), p.tw_sizes[i], st),
+              "row-pass twiddles");
+  }
   if (p.n_tap > 0)
     HIP_TRY(hipMemcpyAsync(ws(p, p.ws_origin), p.origin.data(), p.origin.size() * 4, hipMemcpyHostToDevice, st),
             "upload footprint origins");
@@ -492,6 +530,12 @@ moff_status moff_set_kernels_phased(moff_plan_t plan, const void *d_kern, const 
                                     reinterpret_cast<float2 *>(ws(p, p.ws_wk)), p.n_groups, p.n_ant, p.n_pol,
                                     p.ksize * p.ksize, p.kplanes(), static_cast<hipStream_t>(stream)),
           "pack kernels");
+  if (p.gemm())
+    HIP_TRY(moff::launch_pack_rk(static_cast<const float2 *>(d_kern), static_cast<const float2 *>(d_phase),
+                                 reinterpret_cast<float2 *>(ws(p, p.ws_rk)),
+                                 (int64_t)p.n_chan * p.n_ant * p.n_pol * p.ksize * p.ksize, p.ksize * p.ksize,
+                                 static_cast<hipStream_t>(stream)),
+            "pack row-pass kernels");
   p.kernels_set = true;
   return ok();
 }

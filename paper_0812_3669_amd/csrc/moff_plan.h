@@ -41,6 +41,7 @@ struct Chan {
   int32_t band_count;
   int32_t cols;         // columns per column-pass workgroup
   int32_t col_groups;   // n / cols
+  int32_t rg_first;     // matrix-core row pass: descriptor of row jmin in the row table
 };
 
 // A launch block of the fused path: consecutive channels with the same grid size.
@@ -71,6 +72,12 @@ struct Plan {
   // ((r - row0) * row_stride(n) + i) and the antenna its position in the band's list for sizes whose row pass
   // stages voltages (row_stages_volts), its index otherwise; kidx = a*K*K + y*K + x.  Empty lanes hold antenna 0
   // and a cell no other lane of the group uses, with kidx -1 (zero weights).
+  // matrix-core row pass (MOFF_FFT_GEMM_FP16): per touched row of each channel (jmin .. jmax), (first entry, count)
+  // of its antenna list; entries antenna | (row - j0) << 16 | i0 << 20, ascending antenna; the longest list, and
+  // the samples per time tile the workgroup's LDS holds
+  std::vector<int32_t> rg_rows;         // [rows][2]
+  std::vector<uint32_t> rg_ents;
+  int32_t rg_max_ants = 0, rg_tt = 0;
   std::vector<uint32_t> grp_meta;       // [G][64]
   std::vector<int32_t> grp_kidx;        // [G][64]
   std::vector<int32_t> grp_chan;        // [G] channel of each group
@@ -99,6 +106,9 @@ struct Plan {
   size_t ws_meta = 0, ws_kidx = 0, ws_gchan = 0, ws_wk = 0;  // tap groups; packed kernels float2 [G][64][planes]
   size_t ws_band_ant = 0;               // band antenna lists (int32)
   size_t ws_mfma = 0;                   // split-transform matrices (split fft modes only)
+  size_t ws_rg_rows = 0, ws_rg_ents = 0, ws_rk = 0, ws_rgtw = 0;   // matrix-core row pass: row table, entries,
+                                        // kernels [C][A][P][K][K] with phases folded, w^m tables (one per n)
+  std::vector<size_t> rgtw_off;         // byte offset of each w^m table (order of tw_sizes)
   size_t ws_ring = 0, ws_ctr = 0;       // streaming form: per-XCD ring of row-transformed samples; counters
   size_t ws_tap_tw = 0, ws_tap_twoff = 0, ws_tap_idx = 0, ws_tap_cpix = 0, ws_origin = 0;   // taps
   size_t ws_h = 0, ws_h_bytes = 0;      // row-pass output of one launch block
@@ -137,6 +147,8 @@ struct Plan {
   int kplanes() const { return kernel_mode == MOFF_KERNEL_JONES ? 4 : n_pol; }   // packed kernel planes
   int acc_reals() const { return n_pol == 2 ? 4 : 1; }
   size_t acc_elem_bytes() const { return acc_mode == MOFF_ACC_FP64_COMP ? 16 : 4; }
+  bool gemm() const { return fft_mode == MOFF_FFT_GEMM_FP16; }
+  bool split_mfma() const { return fft_mode == MOFF_FFT_SPLIT_FP16 || fft_mode == MOFF_FFT_SPLIT_BF16; }
   size_t volt_sample_bytes() const {  // one time sample, all channels
     return (size_t)n_chan * n_ant * n_pol * (volt_format == MOFF_VOLT_INT8 ? 2 : 8);
   }
@@ -153,5 +165,8 @@ bool fft_size_supported(int n);
 int band_rows_for(int n, int P);
 int cols_for(int n);
 int smallest_supported_size(int need);
+// LDS bytes of one matrix-core row-pass workgroup: w^m table, taps, first columns and antennas of `slots` antenna
+// slots, `tt` samples of FP16 voltages per slot (row stride slots + 4 words) and one float per wavefront.
+size_t rowgemm_lds_bytes(int n, int K, int slots, int tt);
 
 }  // namespace moff

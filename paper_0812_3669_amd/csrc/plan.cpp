@@ -61,6 +61,10 @@ int cols_for(int n) {
   return w;
 }
 
+size_t rowgemm_lds_bytes(int n, int K, int slots, int tt) {
+  return (size_t)n * 8 + (size_t)slots * K * 8 + (size_t)slots * 8 + (size_t)tt * (slots + 4) * 4 + kWaves * 4;
+}
+
 int smallest_supported_size(int need) {
   static const int ok[] = {32, 64, 96, 128, 160, 192, 256, 320, 384, 512};
   for (int v : ok)
@@ -204,8 +208,11 @@ moff_status build_plan(const moff_plan_desc &d, Plan &p, std::string *err) {
   if (!d.ant_xy_m || !d.freq_hz) return fail(err, MOFF_E_INVALID, "ant_xy_m and freq_hz must be non-null");
   if (!(d.cell_lambda > 0.0) || !std::isfinite(d.cell_lambda))
     return fail(err, MOFF_E_INVALID, "cell_lambda must be positive");
-  if (d.fft_mode != MOFF_FFT_FP32 && d.fft_mode != MOFF_FFT_SPLIT_FP16 && d.fft_mode != MOFF_FFT_SPLIT_BF16)
+  if (d.fft_mode != MOFF_FFT_FP32 && d.fft_mode != MOFF_FFT_SPLIT_FP16 && d.fft_mode != MOFF_FFT_SPLIT_BF16 &&
+      d.fft_mode != MOFF_FFT_GEMM_FP16)
     return fail(err, MOFF_E_INVALID, "unknown fft_mode");
+  if (d.fft_mode == MOFF_FFT_GEMM_FP16 && d.volt_format != MOFF_VOLT_INT8)
+    return fail(err, MOFF_E_UNSUPPORTED, "the matrix-core row pass takes int8 voltages (exact in FP16)");
   if (d.acc_mode != MOFF_ACC_FP32 && d.acc_mode != MOFF_ACC_FP64_COMP)
     return fail(err, MOFF_E_INVALID, "unknown acc_mode");
   if (d.volt_format != MOFF_VOLT_INT8 && d.volt_format != MOFF_VOLT_C64)
@@ -298,7 +305,7 @@ moff_status build_plan(const moff_plan_desc &d, Plan &p, std::string *err) {
     ch.col_groups = n / ch.cols;
   }
   p.pix_total = pix;
-  if (p.fft_mode != MOFF_FFT_FP32) {
+  if (p.split_mfma()) {
     // the matrix-core transform is built for 256^2 grids with two pols
     if (P != 2) return fail(err, MOFF_E_UNSUPPORTED, "split-precision transform needs two pols");
     for (const Chan &ch : p.chans)
@@ -376,6 +383,49 @@ moff_status build_plan(const moff_plan_desc &d, Plan &p, std::string *err) {
     cb = ChanBuild();   // release the channel's copy
   });
   if ((int64_t)p.bands.size() > INT32_MAX / 2) return fail(err, MOFF_E_UNSUPPORTED, "too many bands");
+  // matrix-core row pass: the antennas covering each touched row, in ascending order (a counting sort per channel)
+  p.rg_rows.clear();
+  p.rg_ents.clear();
+  p.rg_max_ants = 0;
+  if (p.gemm()) {
+    for (int c = 0; c < C; ++c) {
+      Chan &ch = p.chans[c];
+      const int rows = ch.jmax - ch.jmin + 1;
+      ch.rg_first = (int32_t)(p.rg_rows.size() / 2);
+      std::vector<int32_t> cnt((size_t)rows + 1, 0);
+      for (int a = 0; a < A; ++a) {
+        const int j0 = p.origin[((size_t)c * A + a) * 2];
+        for (int y = 0; y < K; ++y) ++cnt[(size_t)(j0 + y - ch.jmin) + 1];
+      }
+      for (int r = 0; r < rows; ++r) cnt[(size_t)r + 1] += cnt[(size_t)r];
+      const size_t base = p.rg_ents.size();
+      p.rg_ents.resize(base + (size_t)A * K);
+      std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
+      for (int a = 0; a < A; ++a) {
+        const int j0 = p.origin[((size_t)c * A + a) * 2], i0 = p.origin[((size_t)c * A + a) * 2 + 1];
+        for (int y = 0; y < K; ++y)
+          p.rg_ents[base + (size_t)fill[(size_t)(j0 + y - ch.jmin)]++] =
+              (uint32_t)a | ((uint32_t)y << 16) | ((uint32_t)i0 << 20);
+      }
+      for (int r = 0; r < rows; ++r) {
+        p.rg_rows.push_back((int32_t)(base + (size_t)cnt[(size_t)r]));
+        p.rg_rows.push_back(cnt[(size_t)r + 1] - cnt[(size_t)r]);
+        p.rg_max_ants = std::max(p.rg_max_ants, cnt[(size_t)r + 1] - cnt[(size_t)r]);
+      }
+    }
+    if (p.rg_ents.size() > (size_t)INT32_MAX) return fail(err, MOFF_E_UNSUPPORTED, "row table too large");
+    // samples per time tile: 128 if the workgroup's LDS stays within 80 KB (2 per CU, the register-bound occupancy
+    // of the kernel), else 64, 32 or 16 (divisors of the default 256-sample block: no short tiles)
+    int nmax_rg = 0;
+    for (const Chan &ch : p.chans) nmax_rg = std::max(nmax_rg, ch.n);
+    const int slots = (p.rg_max_ants + 15) / 16 * 16;
+    int tt = 128;
+    while (tt > 16 && rowgemm_lds_bytes(nmax_rg, K, slots, tt) > 80 * 1024) tt /= 2;
+    if (rowgemm_lds_bytes(nmax_rg, K, slots, tt) > 160 * 1024)
+      return fail(err, MOFF_E_UNSUPPORTED, "too many antennas on one grid row for the matrix-core row pass");
+    p.rg_tt = tt;
+  }
+
   // full-grid bands of the staged 2-D FFT: every row, whatever the footprints touch
   p.fft_bands.clear();
   p.fft_band_first.assign((size_t)C + 1, 0);
@@ -424,7 +474,21 @@ moff_status build_plan(const moff_plan_desc &d, Plan &p, std::string *err) {
   p.ws_band_ant = off;
   off = align256(off + p.band_ant.size() * 4);
   p.ws_mfma = off;
-  if (p.fft_mode != MOFF_FFT_FP32) off = align256(off + kMfmaTableBytesHost);
+  if (p.split_mfma()) off = align256(off + kMfmaTableBytesHost);
+  p.rgtw_off.clear();
+  if (p.gemm()) {
+    p.ws_rg_rows = off;
+    off = align256(off + p.rg_rows.size() * 4);
+    p.ws_rg_ents = off;
+    off = align256(off + p.rg_ents.size() * 4);
+    p.ws_rk = off;
+    off = align256(off + (size_t)C * A * P * K * K * 8);
+    p.ws_rgtw = off;
+    for (int n : p.tw_sizes) {
+      p.rgtw_off.push_back(off);
+      off = align256(off + (size_t)n * 8);
+    }
+  }
   // streaming form: kStreamXcds rings of stream_slots row-transformed samples of the largest grid, then the
   // counters [kStreamXcds][2][slots] and the error flag
   p.stream_slots = env_int("MOFF_STREAM_SLOTS", 3, 2, kStreamMaxSlots);

@@ -3,9 +3,10 @@
 2048 antennas in a 200-wavelength disk, 128 channels over 100-130 MHz, two pols, 4x4 kernels, 256^2 grids and all
 16384 samples of device-drawn int8 voltages, run through the C ABI in the launch configuration the benchmark times
 (default launch shape, graph replay, every channel of the plan).  The lowest and the highest channel are checked
-pixel by pixel against the oracle evaluated over the whole integration (computed once for the module), in four
+pixel by pixel against the oracle evaluated over the whole integration (computed once for the module), in six
 arithmetic forms: FP32 transform with the FP32 accumulator, FP32 transform with the FP64 (sum, carry) accumulator,
-and the split FP16 and split BF16 matrix-core transforms with the FP64 (sum, carry) accumulator.  The per-image
+the split FP16 and split BF16 matrix-core transforms with the FP64 (sum, carry) accumulator, and the matrix-core
+row pass (gridding + row DFT as one split-FP16 GEMM) with either accumulator.  The per-image
 errors (XX, YY, XY, YX of each checked channel; max|gpu - oracle| / max|oracle|, the cross products scaled by
 sqrt(max XX max YY)) are printed as a table.
 """
@@ -28,6 +29,8 @@ MODES = [
     ("fp32 transform, fp64 (sum, carry) accumulator", api.FFT_FP32, api.ACC_FP64_COMP),
     ("split fp16 transform, fp64 (sum, carry) accumulator", api.FFT_SPLIT_FP16, api.ACC_FP64_COMP),
     ("split bf16 transform, fp64 (sum, carry) accumulator", api.FFT_SPLIT_BF16, api.ACC_FP64_COMP),
+    ("gemm fp16 row pass, fp32 accumulator", api.FFT_GEMM_FP16, api.ACC_FP32),
+    ("gemm fp16 row pass, fp64 (sum, carry) accumulator", api.FFT_GEMM_FP16, api.ACC_FP64_COMP),
 ]
 
 
@@ -53,7 +56,8 @@ def headline():
 
 
 @pytest.mark.timeout(1200)
-@pytest.mark.parametrize("label,fft,acc", MODES, ids=["fp32", "fp32_acc64", "split_fp16_acc64", "split_bf16_acc64"])
+@pytest.mark.parametrize("label,fft,acc", MODES, ids=["fp32", "fp32_acc64", "split_fp16_acc64", "split_bf16_acc64",
+                                                     "gemm_fp16", "gemm_fp16_acc64"])
 def test_headline_every_pixel(headline, label, fft, acc):
     cfg, geo, kern, volts, sel, ref = headline
     dev = torch.device(DEV)

@@ -178,6 +178,70 @@ def test_fused_every_size(n, P, K, A, C, T, int8):
     _check_images(imgs, ref, label=f"n={n}")
 
 
+# ---------------------------------------------------------------------------------------------------------
+# gridding + row transform as one split-FP16 matrix-core GEMM over time samples (MOFF_FFT_GEMM_FP16)
+# ---------------------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("n,P,K,A,C,T,acc", [
+    (32, 2, 4, 12, 2, 5, api.ACC_FP32), (64, 1, 4, 50, 2, 11, api.ACC_FP32), (96, 2, 2, 30, 1, 3, api.ACC_FP64_COMP),
+    (128, 2, 6, 70, 3, 19, api.ACC_FP32), (160, 2, 4, 33, 1, 4, api.ACC_FP32), (192, 1, 8, 41, 1, 5, api.ACC_FP32),
+    (256, 2, 4, 90, 2, 40, api.ACC_FP32), (256, 2, 4, 300, 2, 33, api.ACC_FP64_COMP), (320, 2, 2, 25, 1, 3, api.ACC_FP32),
+    (384, 2, 6, 44, 1, 3, api.ACC_FP32), (512, 2, 4, 31, 1, 2, api.ACC_FP32),
+])
+def test_gemm_row_pass_every_size(n, P, K, A, C, T, acc):
+    """The matrix-core row pass (gridding + row DFT as a split-FP16 GEMM) against the oracle, every pixel.  The
+    300-antenna 256^2 case puts 60-odd antennas on the middle rows (several K chunks) and 33 samples span three
+    16-sample tiles, the last one ragged."""
+    cfg = _small(n, P=P, A=A, C=C, T=T, K=K, seed=n + 2000 + A)
+    geo, kern, volts = synth.workload(cfg)
+    plan = api.plan_for(cfg, geo, acc_mode=acc, fft_mode=api.FFT_GEMM_FP16).bind(DEV)
+    plan.set_kernels(torch.from_numpy(kern).to(DEV))
+    imgs, _ = _run_fused(plan, volts)
+    ref = ora.image(volts, kern, geo.ant_xy_m, geo.freqs_hz, geo.grid_n, cfg.cell_lambda)
+    _check_images(imgs, ref, label=f"gemm row pass n={n} P={P} K={K}", report=True)
+
+
+def test_gemm_row_pass_default_shape_phases_edges():
+    """The matrix-core row pass at the default launch shape with ragged time and channel blocks (300 samples, 33
+    channels), with phase-centre phases folded into its kernels, and with footprints on the grid edges."""
+    cfg = _small(64, A=30, C=33, T=300, seed=41)
+    geo, kern, volts = synth.workload(cfg)
+    plan = api.plan_for(cfg, geo, fft_mode=api.FFT_GEMM_FP16).bind(DEV)
+    assert plan.launch_shape() == (256, 32, 32)
+    ph = _phases(cfg, 4)
+    plan.set_kernels(torch.from_numpy(kern).to(DEV), phase=torch.from_numpy(ph).to(DEV))
+    imgs, _ = _run_fused(plan, volts)
+    sel = [0, cfg.n_chan - 1]
+    ref = ora.image(ora.apply_phases(volts, ph)[:, sel], kern[sel], geo.ant_xy_m, geo.freqs_hz[sel], geo.grid_n[sel],
+                    cfg.cell_lambda)
+    _check_images([imgs[c] for c in sel], ref, label="gemm default shape, phased")
+    cfg, geo, kern, volts = _edge_setup(256, 4, T=40, seed=5)
+    plan = api.plan_for(cfg, geo, fft_mode=api.FFT_GEMM_FP16).bind(DEV)
+    plan.set_kernels(torch.from_numpy(kern).to(DEV))
+    imgs, _ = _run_fused(plan, volts)
+    _check_images(imgs, ora.image(volts, kern, geo.ant_xy_m, geo.freqs_hz, geo.grid_n, cfg.cell_lambda),
+                  label="gemm edges", report=True)
+
+
+def test_gemm_row_pass_batched_sizes_and_graph():
+    """Per-channel grid sizes 128^2-384^2 with 6x6 kernels (the batched workload's shape, 48 antennas), eager and
+    graph-replayed (bit-identical)."""
+    cfg = configs.scaled(configs.BATCHED, n_ant=48, n_chan=6, n_time=21)
+    geo, kern, volts = synth.workload(cfg)
+    plan = api.plan_for(cfg, geo, fft_mode=api.FFT_GEMM_FP16).bind(DEV)
+    assert len(set(plan.grid_n)) >= 4, plan.grid_n
+    plan.set_kernels(torch.from_numpy(kern).to(DEV))
+    imgs, acc = _run_fused(plan, volts)
+    ref = ora.image(volts, kern, geo.ant_xy_m, geo.freqs_hz, geo.grid_n, cfg.cell_lambda)
+    _check_images(imgs, ref, label="gemm per-channel sizes", report=True)
+    v = torch.from_numpy(volts).to(DEV)
+    g = plan.new_accumulator()
+    for _ in range(2):
+        g.zero_()
+        plan.correlate_graph(v, g)
+        torch.cuda.synchronize()
+        assert torch.equal(g, acc)
+
+
 def test_ragged_time_blocks_and_fp64_accumulator():
     cfg = _small(64, C=3, A=45, T=37)
     for mode in (api.ACC_FP32, api.ACC_FP64_COMP):
