@@ -1,22 +1,27 @@
 """Serving form of the MOFF hot path: continuous batching of correlation jobs on one GPU.
 
 Jobs arrive as a seeded Poisson stream.  Each job has its own array (antenna count), channel count, integration
-length and grid size; it is admitted when a slot is free and its projected HBM (workspace + accumulator +
-kernels + one time block of voltages) fits the budget, otherwise it waits in arrival order.  Admitted jobs
-advance one time block at a time, each on its own HIP stream, so the kernels of different jobs overlap on the
-device; a job's accumulator stays resident until its integration is complete, when its image is read out and
-its latency (completion - arrival) recorded.  Results are deterministic per job: the same job gives the same
-image alone or in a mix.
+length and grid size.  A job is admitted when a slot is free and its projected HBM fits the budget: workspace,
+accumulator, image, kernels, and the voltage blocks in flight.  Admitted jobs advance independently.  Each keeps up
+to ``depth`` time blocks enqueued on its own HIP stream and enqueues the next block as soon as one completes, so a
+small job never waits for a large job's block and the kernels of different jobs overlap on the device.
 
-The scheduler (``Scheduler``) is independent of the device: ``GpuExecutor`` runs jobs through the C ABI,
-``ModelExecutor`` stands in for it with a modelled duration (used by CPU tests of admission, queueing and
-budget handling).
+A job's accumulator stays resident until its integration is complete; then its image is read out and its latency
+(completion - arrival) is recorded.  Admission is re-checked on every pass of the loop.  While the head of the
+queue waits for memory, later jobs that fit are admitted in its place (backfill), for at most ``max_head_wait``
+seconds; after that nothing overtakes the head until it has been admitted.  A job whose set-up, launch or read-out
+raises is marked failed and its memory released, and serving continues.  Results are deterministic per job: the
+same job gives the same image alone or in a mix.
+
+The scheduler (``Scheduler``) is independent of the device.  ``GpuExecutor`` runs jobs through the C ABI.
+``ModelExecutor`` stands in for it with a modelled device (one FIFO queue of blocks, each taking its channel-samples
+/ rate seconds), used by CPU tests of admission, backfill, failure handling and latency accounting.
 """
 from __future__ import annotations
 
-import heapq
 import math
 import time
+from collections import deque
 from dataclasses import dataclass, field
 from typing import Dict, List, Optional
 
@@ -59,8 +64,9 @@ class JobSpec:
 
     @property
     def fft_mode(self) -> str:
-        """The split-precision transform is built for 256^2 grids; other sizes run the FP32 transform."""
-        return self.mode if self.grid_n == 256 else "fp32"
+        """"fp32" (scatter gridding, FP32 transform) or "split_fp16" (gridding and the row transform as one
+        split-FP16 matrix-core GEMM; any grid size)."""
+        return self.mode
 
     def chans_per_launch(self, block: int, cap_bytes: int = 1 << 30) -> int:
         """Channels per launch so that the row-transform buffer (block samples x channels x 2 pols x n^2 x 8 B)
@@ -90,14 +96,14 @@ def make_trace(seed: int = 4000, n_jobs: int = 256, rate: float = 200.0, time_sc
     return out
 
 
-def hbm_bytes(spec: JobSpec, block: int, plan_ws: Optional[int] = None) -> int:
-    """Projected device memory of a job: accumulator (4 FP32 reals per pixel), image, kernels, one block of
+def hbm_bytes(spec: JobSpec, block: int, plan_ws: Optional[int] = None, depth: int = 1) -> int:
+    """Projected device memory of a job: accumulator (4 FP32 reals per pixel), image, kernels, ``depth`` blocks of
     voltages, and the plan workspace (tap tables + row-transform buffer of one launch block)."""
     pix = spec.n_chan * spec.grid_n ** 2
     acc = pix * 4 * 4
     img = pix * 4 * 8
     kern = spec.n_chan * spec.n_ant * 2 * 16 * 8
-    volt = block * spec.n_chan * spec.n_ant * 2 * 2
+    volt = depth * block * spec.n_chan * spec.n_ant * 2 * 2
     ws = plan_ws if plan_ws is not None else (kern + min(16, spec.n_chan) * 16 * 2 * spec.grid_n ** 2 * 8)
     return int(acc + img + kern + volt + ws)
 
@@ -106,7 +112,7 @@ def hbm_bytes(spec: JobSpec, block: int, plan_ws: Optional[int] = None) -> int:
 class JobState:
     spec: JobSpec
     admitted: float = 0.0
-    done_samples: int = 0
+    enqueued: int = 0          # samples enqueued so far
     finished: float = 0.0
     hbm: int = 0
     handle: object = None
@@ -117,109 +123,184 @@ class Stats:
     latencies: List[float] = field(default_factory=list)
     admitted: int = 0
     rejected: int = 0
+    failed: int = 0
+    backfilled: int = 0
     peak_concurrent: int = 0
     channel_samples: int = 0
     wall: float = 0.0
     results: Dict[int, object] = field(default_factory=dict)
+    errors: Dict[int, str] = field(default_factory=dict)
+    order: List[int] = field(default_factory=list)      # job ids in admission order
 
     def summary(self) -> dict:
         lat = np.array(self.latencies) if self.latencies else np.zeros(1)
         return {"jobs_completed": len(self.latencies), "admitted": self.admitted, "rejected": self.rejected,
-                "peak_concurrent": self.peak_concurrent,
+                "failed": self.failed, "backfilled": self.backfilled, "peak_concurrent": self.peak_concurrent,
                 "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
                 "channel_samples": self.channel_samples, "wall_s": self.wall,
                 "channel_samples_per_s": self.channel_samples / self.wall if self.wall > 0 else 0.0}
 
 
 class Scheduler:
-    """Admission by HBM budget and slots, arrival-order queue, one time block per active job per round."""
+    """Admission by HBM budget and slots with bounded backfill; every job advances on its own completions."""
 
-    def __init__(self, executor, hbm_budget: int, max_slots: int = 8, block: int = 64,
-                 keep_results: bool = False, progress=None):
+    def __init__(self, executor, hbm_budget: int, max_slots: int = 8, block: int = 64, depth: int = 2,
+                 max_head_wait: float = 2.0, keep_results: bool = False, progress=None):
         self.progress = progress        # optional callable(completed, total), called as jobs complete
         self.ex = executor
         self.budget = hbm_budget
         self.max_slots = max_slots
         self.block = block
+        self.depth = depth              # time blocks a job keeps enqueued
+        self.max_head_wait = max_head_wait
         self.keep = keep_results
+
+    def _fail(self, st: Stats, spec: JobSpec, err: BaseException):
+        st.failed += 1
+        st.errors[spec.job_id] = f"{type(err).__name__}: {err}"
 
     def run(self, trace: List[JobSpec], realtime: bool = True) -> Stats:
         st = Stats()
+        ex = self.ex
         pending = sorted(trace, key=lambda s: s.arrival)
         queue: List[JobSpec] = []
         active: List[JobState] = []
         used = 0
-        t_start = self.ex.now()
+        t_start = ex.now()
+        head_since: Optional[float] = None    # when the current head of the queue started waiting for memory
+        head_id: Optional[int] = None
         i = 0
         while i < len(pending) or queue or active:
-            now = self.ex.now() - t_start
+            now = ex.now() - t_start
             if not realtime and not queue and not active and i < len(pending):
-                self.ex.advance_to(t_start + pending[i].arrival)
-                now = self.ex.now() - t_start
+                ex.advance_to(t_start + pending[i].arrival)
+                now = ex.now() - t_start
             while i < len(pending) and pending[i].arrival <= now:
                 spec = pending[i]
                 i += 1
-                self.ex.prefetch(spec, self.block)   # host set-up (instrument, plan) starts in the background
+                ex.prefetch(spec, self.block)   # host set-up (instrument, plan) starts in the background
                 queue.append(spec)
-            # admit in arrival order while a slot and memory are free; a job whose set-up is still running holds
-            # the head of the queue; one that can never fit is rejected when it reaches the head
-            while queue and len(active) < self.max_slots and self.ex.ready(queue[0]):
-                spec = queue[0]
-                need = self.ex.hbm(spec, self.block)
-                if need > self.budget:
-                    queue.pop(0)
-                    st.rejected += 1
-                    self.ex.discard(spec)
-                    continue
-                if used + need > self.budget:
-                    break
-                queue.pop(0)
-                js = JobState(spec, admitted=now, hbm=need)
-                js.handle = self.ex.start(spec, self.block)
-                used += need
-                active.append(js)
-                st.admitted += 1
+            progressed, waiting = self._admit(st, queue, active, now, head_since)
+            # the head waits for memory: note since when (backfill past it stops after max_head_wait)
+            if waiting is None:
+                head_since, head_id = None, None
+            elif waiting != head_id:
+                head_since, head_id = now, waiting
             st.peak_concurrent = max(st.peak_concurrent, len(active))
-            if not active:
-                if queue:
-                    self.ex.sleep(0.001)            # the head job's set-up is still running
-                elif i < len(pending):
-                    wait = t_start + pending[i].arrival - self.ex.now()
-                    if wait > 0:
-                        self.ex.sleep(wait)
+            # advance every active job on its own completions
+            for js in list(active):
+                try:
+                    ex.poll(js.handle)
+                    while js.enqueued < js.spec.n_time and ex.in_flight(js.handle) < self.depth:
+                        nt = min(self.block, js.spec.n_time - js.enqueued)
+                        ex.step(js.handle, js.enqueued, nt)
+                        js.enqueued += nt
+                        progressed = True
+                    if js.enqueued >= js.spec.n_time and ex.in_flight(js.handle) == 0:
+                        img = ex.finish(js.handle)
+                        js.finished = ex.now() - t_start
+                        st.latencies.append(js.finished - js.spec.arrival)
+                        st.channel_samples += js.spec.channel_samples
+                        if self.keep:
+                            st.results[js.spec.job_id] = img
+                        active.remove(js)
+                        progressed = True
+                        if self.progress:
+                            self.progress(len(st.latencies), len(pending))
+                except Exception as e:    # the job fails; the others keep running
+                    self._fail(st, js.spec, e)
+                    ex.release(js.handle)
+                    active.remove(js)
+                    progressed = True
+            if progressed:
                 continue
-            # one block of every active job, enqueued back to back (their streams overlap on the device)
-            for js in active:
-                if js.done_samples < js.spec.n_time:
-                    nt = min(self.block, js.spec.n_time - js.done_samples)
-                    self.ex.step(js.handle, js.done_samples, nt)
-                    js.done_samples += nt
-            self.ex.wait_round([js.handle for js in active])
-            finished = [js for js in active if js.done_samples >= js.spec.n_time]
-            for js in finished:
-                img = self.ex.finish(js.handle)
-                js.finished = self.ex.now() - t_start
-                st.latencies.append(js.finished - js.spec.arrival)
-                st.channel_samples += js.spec.channel_samples
-                if self.progress:
-                    self.progress(len(st.latencies), len(pending))
-                if self.keep:
-                    st.results[js.spec.job_id] = img
-                used -= js.hbm
-                active.remove(js)
-        st.wall = self.ex.now() - t_start
+            if active:
+                ex.wait_any([js.handle for js in active])
+            elif queue:
+                ex.sleep(0.001)            # a queued job's set-up is still running
+            elif i < len(pending):
+                wait = t_start + pending[i].arrival - ex.now()
+                if wait > 0:
+                    ex.sleep(wait)
+        st.wall = ex.now() - t_start
         return st
+
+    def _need(self, spec, st, queue):
+        """Projected HBM of a job whose set-up is done, or None (set-up failed: the job is failed and dropped)."""
+        try:
+            return self.ex.hbm(spec, self.block, self.depth)
+        except Exception as e:
+            self._fail(st, spec, e)
+            queue.remove(spec)
+            self.ex.discard(spec)
+            return None
+
+    def _admit(self, st, queue, active, now, head_since):
+        """One admission pass in arrival order.  The first job in the queue that is ready is the head; it is
+        admitted if a slot and its memory are free.  While it waits for memory, later ready jobs that fit are
+        admitted in its place (backfill) unless it has waited max_head_wait seconds.  Jobs whose set-up is still
+        running are skipped; a job that can never fit the budget is rejected when reached.  Returns (progressed,
+        job id of the head if it is waiting for memory, else None)."""
+        ex = self.ex
+        progressed = False
+        used = sum(js.hbm for js in active)
+        waiting = None                 # the head, when it waits for memory
+        for spec in list(queue):
+            if len(active) >= self.max_slots:
+                break
+            if not ex.ready(spec):
+                continue
+            need = self._need(spec, st, queue)
+            if need is None:
+                progressed = True
+                continue
+            if need > self.budget:
+                queue.remove(spec)
+                st.rejected += 1
+                ex.discard(spec)
+                progressed = True
+                continue
+            if used + need > self.budget:
+                if waiting is None:
+                    waiting = spec.job_id
+                    if head_since is not None and now - head_since >= self.max_head_wait:
+                        break          # the head has waited long enough: nothing overtakes it
+                continue
+            queue.remove(spec)
+            try:
+                handle = ex.start(spec, self.block)
+            except Exception as e:
+                self._fail(st, spec, e)
+                ex.discard(spec)
+                progressed = True
+                continue
+            active.append(JobState(spec, admitted=now, hbm=need, handle=handle))
+            used += need
+            st.admitted += 1
+            st.order.append(spec.job_id)
+            if waiting is not None:
+                st.backfilled += 1
+            progressed = True
+        return progressed, waiting
 
 
 class ModelExecutor:
-    """Device stand-in: a job block takes cs / rate seconds of modelled time (no GPU, no real sleeping)."""
+    """Device stand-in: one FIFO queue of blocks, each taking its channel-samples / rate seconds of modelled time
+    (grids scaled by (n / 256)^2), with no GPU and no real sleeping.  ``fail`` maps job ids to the call that raises
+    for them ("prepare", "start", "step" or "finish"), to test failure handling."""
 
-    def __init__(self, cs_per_s: float = 2e6, hbm_scale: float = 1.0):
+    def __init__(self, cs_per_s: float = 2e6, hbm_scale: float = 1.0, fail: Optional[Dict[int, str]] = None):
         self.t = 0.0
         self.rate = cs_per_s
         self.hbm_scale = hbm_scale
+        self.fail = dict(fail or {})
         self.started: List[int] = []
-        self._round = 0.0
+        self.released: List[int] = []
+        self.device_free = 0.0
+
+    def _maybe_fail(self, spec, where):
+        if self.fail.get(spec.job_id) == where:
+            raise RuntimeError(f"modelled {where} failure of job {spec.job_id}")
 
     def now(self):
         return self.t
@@ -230,8 +311,9 @@ class ModelExecutor:
     def advance_to(self, t):
         self.t = max(self.t, t)
 
-    def hbm(self, spec, block):
-        return int(hbm_bytes(spec, block) * self.hbm_scale)
+    def hbm(self, spec, block, depth=1):
+        self._maybe_fail(spec, "prepare")
+        return int(hbm_bytes(spec, block, depth=depth) * self.hbm_scale)
 
     def prefetch(self, spec, block):
         pass
@@ -243,19 +325,35 @@ class ModelExecutor:
         pass
 
     def start(self, spec, block):
+        self._maybe_fail(spec, "start")
         self.started.append(spec.job_id)
-        return {"spec": spec}
+        return {"spec": spec, "inflight": deque()}
 
     def step(self, h, t0, nt):
+        self._maybe_fail(h["spec"], "step")
         cost = h["spec"].n_chan * nt * (h["spec"].grid_n / 256.0) ** 2 / self.rate
-        self._round += cost
+        begin = max(self.device_free, self.t)
+        self.device_free = begin + cost
+        h["inflight"].append(self.device_free)
 
-    def wait_round(self, handles):
-        self.t += self._round
-        self._round = 0.0
+    def poll(self, h):
+        while h["inflight"] and h["inflight"][0] <= self.t:
+            h["inflight"].popleft()
+
+    def in_flight(self, h):
+        return len(h["inflight"])
+
+    def wait_any(self, handles):
+        due = [h["inflight"][0] for h in handles if h["inflight"]]
+        if due:
+            self.t = max(self.t, min(due))
 
     def finish(self, h):
+        self._maybe_fail(h["spec"], "finish")
         return None
+
+    def release(self, h):
+        self.released.append(h["spec"].job_id)
 
 
 class GpuExecutor:
@@ -316,7 +414,7 @@ class GpuExecutor:
     def _prepare(self, spec, block):
         from . import api
         site = self._site(spec)
-        fft = {"fp32": api.FFT_FP32, "split_fp16": api.FFT_SPLIT_FP16}[spec.fft_mode]
+        fft = {"fp32": api.FFT_FP32, "split_fp16": api.FFT_GEMM_FP16}[spec.fft_mode]
         return api.plan_for(spec.site_config(), site["geo"], fft_mode=fft, time_block=block,
                             chans_per_block=spec.chans_per_launch(block))
 
@@ -333,7 +431,9 @@ class GpuExecutor:
         self.prefetch(spec, block)
         return self._plans[spec.job_id].result()
 
-    def hbm(self, spec, block):
+    def hbm(self, spec, block, depth=1):
+        """Device footprint of a job: its blocks are ordered on one stream and share one voltage buffer, so the
+        blocks in flight add no memory."""
         plan = self._plan(spec, block)
         kern = spec.n_chan * spec.n_ant * 2 * 16 * 8
         volt = block * spec.n_chan * spec.n_ant * 2 * 2
@@ -361,30 +461,60 @@ class GpuExecutor:
             acc = plan.new_accumulator()
             gen = synth.DeviceVoltages(cfg, site["geo"], site["g"], sk, self.device, chunk=block)
             vbuf = torch.empty((block, cfg.n_chan, cfg.n_ant, cfg.n_pol, 2), dtype=torch.int8, device=self.device)
-        ev = torch.cuda.Event()
-        return {"spec": spec, "plan": plan, "acc": acc, "gen": gen, "vbuf": vbuf, "stream": stream, "ev": ev,
-                "site_key": key, "block": block}
+        return {"spec": spec, "plan": plan, "acc": acc, "gen": gen, "vbuf": vbuf, "stream": stream,
+                "events": deque(), "site_key": key, "block": block}
 
     def step(self, h, t0, nt):
+        """Enqueues one block (voltage synthesis, then the correlation) on the job's stream; an event marks its end.
+        Blocks of one job are ordered by its stream, so they share the voltage buffer."""
         torch = self.torch
         with torch.cuda.stream(h["stream"]):
             v = h["vbuf"][:nt]
             h["gen"].chunk_into(t0 // h["block"], v)
             h["plan"].correlate(v, h["acc"], n_t=nt, stream=h["stream"])
-            h["ev"].record(h["stream"])
+            ev = torch.cuda.Event()
+            ev.record(h["stream"])
+        h["events"].append(ev)
 
-    def wait_round(self, handles):
-        for h in handles:
-            h["ev"].synchronize()
+    def poll(self, h):
+        while h["events"] and h["events"][0].query():
+            h["events"].popleft()
+
+    def in_flight(self, h):
+        return len(h["events"])
+
+    def wait_any(self, handles):
+        """Returns once some job's oldest block has finished (polling every 0.2 ms, so the loop never blocks on one
+        job while another could be fed)."""
+        while True:
+            for h in handles:
+                if h["events"] and h["events"][0].query():
+                    return
+            if not any(h["events"] for h in handles):
+                return
+            time.sleep(0.0002)
+
+    def _drop(self, h):
+        dev = self._site_dev.get(h["site_key"])
+        if dev is not None:
+            dev[1] -= 1
+            if dev[1] == 0:
+                del self._site_dev[h["site_key"]]   # free the device copy; the host copy stays cached
+        self._plans.pop(h["spec"].job_id, None)
 
     def finish(self, h):
         torch = self.torch
         with torch.cuda.stream(h["stream"]):
             img = h["plan"].read_image(h["acc"], n_samples=h["spec"].n_time, stream=h["stream"], split=False)
         h["stream"].synchronize()
-        dev = self._site_dev[h["site_key"]]
-        dev[1] -= 1
-        if dev[1] == 0:
-            del self._site_dev[h["site_key"]]   # free the device copy; the host copy stays cached
-        self._plans.pop(h["spec"].job_id, None)
+        self._drop(h)
         return img
+
+    def release(self, h):
+        """A failed job: wait for what its stream holds (an error there is the job's own), then free its memory."""
+        try:
+            h["stream"].synchronize()
+        except Exception:
+            pass
+        h["events"].clear()
+        self._drop(h)

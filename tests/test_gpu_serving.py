@@ -1,5 +1,6 @@
 """Serving form on the GPU: jobs admitted by HBM budget, overlapping on their own streams; each job's image is
-the same alone and in a mix (bit for bit), and a small job matches the oracle."""
+the same alone and in a mix (bit for bit); small FP32 and split-FP16 jobs match the oracle; a job whose set-up
+fails (forced on the host) is counted failed while the others complete."""
 import time
 
 import numpy as np
@@ -25,8 +26,8 @@ OTHERS = [
 ]
 
 
-def _run(trace, slots):
-    ex = serve.GpuExecutor(DEV)
+def _run(trace, slots, ex=None):
+    ex = ex or serve.GpuExecutor(DEV)
     # every job's host set-up is finished before the trace starts, so admission is bounded by the slots alone and
     # the mix overlaps however fast the jobs run
     for j in trace:
@@ -54,8 +55,9 @@ def test_each_job_same_alone_and_in_the_mix():
         assert torch.equal(alone[j.job_id], st.results[j.job_id].cpu()), j
 
 
-def test_small_job_against_oracle():
-    j = JOBS[0]
+@pytest.mark.parametrize("j", [JOBS[0], serve.JobSpec(7, 0.0, 256, 16, 80, 128, "split_fp16", seed=17)],
+                         ids=["fp32", "split_fp16"])
+def test_small_job_against_oracle(j):
     st = _run([j], 1)
     img = st.results[j.job_id].cpu().numpy().astype(np.complex128)
     cfg, scfg = j.config(), j.site_config()
@@ -71,3 +73,21 @@ def test_small_job_against_oracle():
         got = img[c * 4 * n * n:(c + 1) * 4 * n * n].reshape(4, n, n)
         e = ora.relative_errors(got, ref[k])
         assert np.all(e <= TOL), (c, e)
+
+
+class _FailingSetup(serve.GpuExecutor):
+    """Host-side failure: the plan of one job cannot be built (as a plan the library rejects would be)."""
+
+    def _prepare(self, spec, block):
+        if spec.job_id == 99:
+            raise RuntimeError("plan rejected for job 99")
+        return super()._prepare(spec, block)
+
+
+def test_failed_job_does_not_stop_the_others():
+    mix = JOBS + [serve.JobSpec(99, 0.0, 256, 16, 64, 128, "fp32", seed=99)]
+    st = _run(mix, 4, ex=_FailingSetup(DEV))
+    s = st.summary()
+    assert s["failed"] == 1 and 99 in st.errors and s["jobs_completed"] == len(JOBS), (s, st.errors)
+    alone = _run([JOBS[0]], 1)
+    assert torch.equal(alone.results[0].cpu(), st.results[0].cpu())
