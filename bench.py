@@ -25,6 +25,12 @@ sys.path.insert(0, ROOT)
 PEAK_FP32_VECTOR = 157.3e12    # MI355X published FP32 vector peak (packed FP32), FLOP/s
 PEAK_HBM = 8.0e12              # MI355X HBM3E, B/s
 PEAK_MFMA_16 = 2.5e15          # MI355X published dense FP16 / BF16 matrix-core peak, FLOP/s
+# Ceilings measured on the box (profiles/peaks_probe.md, profiles/k_rows_k_cols_headline_fp32_traffic.md): the FP32
+# FMA issue rate of this build (packed FP32 disabled), the FP16 matrix-core instruction rate, and a plain 1 GiB
+# device copy (read + write).
+MEASURED_FP32_FMA = 119.5e12
+MEASURED_MFMA_16 = 1290.6e12
+MEASURED_COPY = 5.08e12
 # Matrix-core form: a 256-point transform is two radix-16 stages, each 16 complex 16-point DFTs done as real
 # GEMMs (4096 complex MACs = 32768 flops per stage), once per split product (FP16 hi/lo: 3, BF16 hi/mid/lo: 6).
 # rocprofv3 SQ_INSTS_VALU_MFMA_MOPS_F16 / _BF16 x 512 reads the same count per launch.
@@ -32,7 +38,8 @@ MFMA_FLOPS_PER_TRANSFORM = 2 * 16 * 16 * 16 * 8
 SPLIT_PRODUCTS = {"split_fp16": 3, "split_bf16": 6}
 
 
-KERNEL_SOURCES = ("kernels.hip", "kernels_mfma.hip", "kernels.h", "fft_radix.h", "fft_sizes.h", "mfma_fft.h")
+KERNEL_SOURCES = ("kernels.hip", "kernels_mfma.hip", "kernels_rowgemm.hip", "kernels.h", "fft_radix.h", "fft_sizes.h",
+                  "mfma_fft.h")
 
 
 def _src_hash() -> str:
@@ -45,10 +52,10 @@ def _src_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def _traffic(kernel: str, launch_cs: int):
-    """HBM bytes per launch of ``kernel`` from the committed rocprofv3 PMC summary (FETCH_SIZE and WRITE_SIZE,
-    each scaled by what the counter reads for a plain 1 GiB device copy), if it was taken on the current kernel
-    sources and the same channel-samples per launch; else None."""
+def _traffic(form: str, kernel: str, launch_cs: int):
+    """HBM bytes per launch of ``kernel`` in arithmetic form ``form`` from the committed rocprofv3 PMC summary
+    (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads for a plain 1 GiB device copy), if it was taken
+    on the current kernel sources and the same channel-samples per launch; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -56,29 +63,29 @@ def _traffic(kernel: str, launch_cs: int):
         d = json.load(open(path))
     except Exception:
         return None
-    k = d.get("kernels", {}).get(kernel)
+    k = d.get("forms", {}).get(form, {}).get(kernel)
     if d.get("src_hash") != _src_hash() or not k or k.get("channel_samples_per_launch") != launch_cs:
         return None
     return k.get("bytes_per_launch")
 
 
+# the headline workload's fused-path kernels per arithmetic form
+TRAFFIC_FORMS = {"fp32": ("k_rows", "k_cols"), "gemm_fp16": ("k_rowgemm", "k_cols"),
+                 "split_fp16": ("k_rows_mfma", "k_cols_mfma")}
 TRAFFIC_COMMANDS = [   # {dir}: the directory given to --write-traffic
-    "rocprofv3 --pmc FETCH_SIZE --output-format csv -d {dir}/pmc_FETCH_SIZE -o run -- python3 -u bench.py "
-    "--time 512 --steps 1 --warmup 1 --no-cpu-baseline --eager",
-    "rocprofv3 --pmc WRITE_SIZE --output-format csv -d {dir}/pmc_WRITE_SIZE -o run -- python3 -u bench.py "
-    "--time 512 --steps 1 --warmup 1 --no-cpu-baseline --eager",
-    "rocprofv3 --pmc FETCH_SIZE --output-format csv -d {dir}/pmccopy_FETCH_SIZE -o run -- python3 -u bench.py "
-    "--calibrate-copy",
-    "rocprofv3 --pmc WRITE_SIZE --output-format csv -d {dir}/pmccopy_WRITE_SIZE -o run -- python3 -u bench.py "
-    "--calibrate-copy",
-]
+    "rocprofv3 --pmc %s --output-format csv -d {dir}/pmc_%s_%s -o run -- python3 -u bench.py --time 512 --steps 1 "
+    "--warmup 1 --no-cpu-baseline --eager --fft %s" % (c, f, c, f)
+    for f in TRAFFIC_FORMS for c in ("FETCH_SIZE", "WRITE_SIZE")] + [
+    "rocprofv3 --pmc %s --output-format csv -d {dir}/pmccopy_%s -o run -- python3 -u bench.py --calibrate-copy" % (c, c)
+    for c in ("FETCH_SIZE", "WRITE_SIZE")]
 
 
 def write_traffic(pmc_dir: str, launch_cs: int = 8192, out_path: str | None = None) -> dict:
-    """Reduces the four rocprofv3 --pmc runs of ``TRAFFIC_COMMANDS`` (CSV output under ``pmc_dir``) to
-    ``profiles/traffic.json``: per fused-path kernel, FETCH_SIZE and WRITE_SIZE (KiB per dispatch, averaged over
-    dispatches), each scaled by copy bytes / counter reading of the 1 GiB device copy; keyed by the kernel
-    sources' hash.  The default launch shape (256 samples x 32 channels) gives ``launch_cs`` channel-samples."""
+    """Reduces the rocprofv3 --pmc runs of ``TRAFFIC_COMMANDS`` (CSV output under ``pmc_dir``) to
+    ``profiles/traffic.json``: per arithmetic form and fused-path kernel, FETCH_SIZE and WRITE_SIZE (KiB per
+    dispatch, averaged over dispatches), each scaled by copy bytes / counter reading of the 1 GiB device copy; keyed
+    by the kernel sources' hash.  The default launch shape (256 samples x 32 channels) gives ``launch_cs``
+    channel-samples."""
     import collections
     import csv
 
@@ -98,22 +105,36 @@ def write_traffic(pmc_dir: str, launch_cs: int = 8192, out_path: str | None = No
     copy_kib = (1 << 30) / 1024
     scale = {c: copy_kib / pick(per_dispatch("pmccopy_" + c), "__amd_rocclr_copyBuffer")[1]
              for c in ("FETCH_SIZE", "WRITE_SIZE")}
-    fetch, write = per_dispatch("pmc_FETCH_SIZE"), per_dispatch("pmc_WRITE_SIZE")
-    kernels = {}
-    for k in ("k_rows", "k_cols"):
-        f = pick(fetch, f"void moff::{k}<")[1]
-        w = pick(write, f"void moff::{k}<")[1]
-        kernels[k] = {"channel_samples_per_launch": launch_cs, "fetch_kib": round(f), "write_kib": round(w),
-                      "bytes_per_launch": round((f * scale["FETCH_SIZE"] + w * scale["WRITE_SIZE"]) * 1024)}
+    forms = {}
+    for form, kernels in TRAFFIC_FORMS.items():
+        fetch, write = per_dispatch(f"pmc_{form}_FETCH_SIZE"), per_dispatch(f"pmc_{form}_WRITE_SIZE")
+        forms[form] = {}
+        for k in kernels:
+            f = pick(fetch, f"void moff::{k}<")[1]
+            w = pick(write, f"void moff::{k}<")[1]
+            forms[form][k] = {"channel_samples_per_launch": launch_cs, "fetch_kib": round(f), "write_kib": round(w),
+                              "bytes_per_launch": round((f * scale["FETCH_SIZE"] + w * scale["WRITE_SIZE"]) * 1024)}
     d = {"src_hash": _src_hash(),
          "note": "rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE per dispatch (KiB), each scaled by what the counter reads "
                  "for a plain 1 GiB device copy (FETCH x%.3f, WRITE x%.3f)" % (scale["FETCH_SIZE"],
                                                                               scale["WRITE_SIZE"]),
-         "commands": [c.format(dir=pmc_dir) for c in TRAFFIC_COMMANDS], "kernels": kernels}
+         "commands": [c.format(dir=pmc_dir) for c in TRAFFIC_COMMANDS], "forms": forms}
     with open(out_path or os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
         json.dump(d, fh, indent=1)
         fh.write("\n")
     return d
+
+
+def rowgemm_mfma_flops(geo, cfg, c: int, n: int) -> float:
+    """Matrix-core flops per sample of the GEMM row pass for channel c (grid n): per touched row and pol, 16-column
+    chunks x antenna chunks of 16 (the row's list rounded up) x four 16x16x32 products, per 16 samples."""
+    import numpy as np
+    K = cfg.ksize
+    y = geo.ant_xy_m[:, 1] * geo.freqs_hz[c] / 299792458.0 / cfg.cell_lambda + n / 2
+    j0 = np.floor(y).astype(np.int64) - K // 2 + 1
+    cnt = np.bincount((j0[:, None] + np.arange(K)[None, :]).ravel(), minlength=n)
+    kc = (cnt[j0.min():j0.max() + K] + 15) // 16
+    return float(cfg.n_pol * (n // 16) * 4 * 16384 * kc.sum() / 16)
 
 
 def cpu_baseline(cfg, geo, kern_np, volts_dev, budget_s: float = 12.0):
@@ -204,6 +225,8 @@ def main():
     ap.add_argument("--time", type=int, default=0, help="samples per step (default: the full 16384)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="tune the launch shape on the first 256 samples")
+    ap.add_argument("--autotune-cache", metavar="FILE",
+                    help="with --autotune: the persisted autotuner cache (a shape tuned before is reused)")
     ap.add_argument("--eager", action="store_true", help="launch kernel by kernel instead of replaying a HIP graph")
     ap.add_argument("--calibrate-copy", action="store_true", help="run a 1 GiB device copy (PMC calibration)")
     ap.add_argument("--write-traffic", metavar="DIR", help="write profiles/traffic.json from the PMC runs under DIR")
@@ -296,7 +319,7 @@ def main():
     acc = plan.new_accumulator()
     tuned = None
     if args.autotune:
-        tuned = plan.autotune(volts, acc, n_t=min(T, 256))
+        tuned = plan.autotune(volts, acc, n_t=min(T, 256), cache=args.autotune_cache)
         print(f"bench: autotuned launch shape {tuned}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     print("bench: workload resident; warmup", file=sys.stderr, flush=True)
@@ -348,6 +371,7 @@ def main():
 
     names = {0: "k_rowgemm" if args.fft == "gemm_fp16" else "k_rows", 1: "k_cols", 2: "k_stream"}
     split = args.fft in SPLIT_PRODUCTS
+    mfma_step = {}
     if split:
         # the matrix-core passes transform every row of the touched bands and every column (256^2, two pols)
         names = {0: "k_rows_mfma", 1: "k_cols_mfma"}
@@ -357,27 +381,54 @@ def main():
         per_transform = MFMA_FLOPS_PER_TRANSFORM * SPLIT_PRODUCTS[args.fft]
         mfma_step = {0: (len(band_ptr) - 1) * int(band_rows[0]) * P * T * per_transform,
                      1: cfg.n_chan * 256 * P * T * per_transform}
+    elif args.fft == "gemm_fp16":
+        mfma_step = {0: T * sum(rowgemm_mfma_flops(geo, cfg, c, n) for c, n in enumerate(plan.grid_n))}
     kt = {}
     for kind in (0, 1, 2):
         tot_ms, launches, kcs = plan.profile_read(kind)
         if launches == 0:
             continue
         # the profiled step covers every channel for T samples; split its channel-samples by grid size
-        step_flops = mfma_step[kind] if split else sum(T * pass_flops(kind, n) for n in plan.grid_n)
-        kt[kind] = dict(ms=tot_ms, launches=launches, cs=kcs, flops=step_flops * kcs / (T * cfg.n_chan))
+        step_flops = sum(T * pass_flops(kind, n) for n in plan.grid_n)
+        frac_cs = kcs / (T * cfg.n_chan)
+        kt[kind] = dict(ms=tot_ms, launches=launches, cs=kcs, flops=step_flops * frac_cs,
+                        mfma_flops=mfma_step.get(kind, 0.0) * frac_cs)
     dom = max(kt, key=lambda k: kt[k]["ms"])
     d = kt[dom]
-    avg_ms = d["ms"] / max(d["launches"], 1)
-    per_launch_flops = d["flops"] / max(d["launches"], 1)
-    achieved = per_launch_flops / (avg_ms / 1e3)
+    nl = max(d["launches"], 1)
+    avg_ms = d["ms"] / nl
+    launch_cs = round(d["cs"] / nl)
     tot_ms_all = sum(v["ms"] for v in kt.values())
-    peak = PEAK_MFMA_16 if split else PEAK_FP32_VECTOR
-    roofline = {"bound": "mfma" if split else "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / peak,
-                "traffic": _traffic(names[dom], round(d["cs"] / max(d["launches"], 1)))
-                if args.workload == "headline" and not split else None,
-                "kernel": names[dom], "avg_launch_ms": avg_ms,
-                "kernel_share": {names[k]: kt[k]["ms"] / tot_ms_all for k in kt}}
+    traffic = _traffic(args.fft, names[dom], launch_cs) if args.workload == "headline" else None
+    if d["mfma_flops"] > 0:
+        # a matrix-core kernel: its own split-FP16/BF16 products against the dense matrix-core peak
+        achieved = d["mfma_flops"] / nl / (avg_ms / 1e3)
+        roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_MFMA_16 / 1e12, "unit": "TFLOP/s",
+                    "frac": achieved / PEAK_MFMA_16, "traffic": traffic,
+                    "measured_ceiling": {"what": "FP16 matrix-core instruction rate (moff_probe)",
+                                         "value": MEASURED_MFMA_16 / 1e12, "frac": achieved / MEASURED_MFMA_16}}
+    else:
+        # algorithmically the path is arithmetic-bound (12 MFLOP per 8.4 KB of voltages at the headline): the FP32
+        # vector units, whose published peak assumes packed FP32 instructions (disabled in this build)
+        achieved = d["flops"] / nl / (avg_ms / 1e3)
+        roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s",
+                    "frac": achieved / PEAK_FP32_VECTOR, "traffic": traffic,
+                    "measured_ceiling": {"what": "FP32 FMA issue rate of this build (moff_probe)",
+                                         "value": MEASURED_FP32_FMA / 1e12, "frac": achieved / MEASURED_FP32_FMA}}
+    roofline.update({"kernel": names[dom], "avg_launch_ms": avg_ms, "channel_samples_per_launch": launch_cs,
+                     "kernel_share": {names[k]: kt[k]["ms"] / tot_ms_all for k in kt}})
+    if traffic:
+        # what the kernel as built moves: the row-to-column exchange, far above the algorithmic bytes.  Its
+        # arithmetic intensity against the ridge (peak flops / 8 TB/s) says which roof binds it.
+        gbs = traffic / (avg_ms / 1e3)
+        intensity = (d["mfma_flops"] if d["mfma_flops"] > 0 else d["flops"]) / nl / traffic
+        ridge = (PEAK_MFMA_16 if d["mfma_flops"] > 0 else PEAK_FP32_VECTOR) / PEAK_HBM
+        roofline["limiter"] = {
+            "measured_bytes_per_launch": traffic,
+            "algorithmic_bytes_per_launch": launch_cs * cfg.volt_bytes_per_cs(),
+            "achieved_gbs": gbs / 1e9, "frac_hbm_peak": gbs / PEAK_HBM, "frac_measured_copy": gbs / MEASURED_COPY,
+            "flop_per_byte": intensity, "ridge_flop_per_byte": ridge,
+            "binding_roof": "hbm" if intensity < ridge else roofline["bound"]}
     algo_flops_step = sum(T * cfg.flops_per_cs(n) for n in plan.grid_n)
     if args.workload == "headline":
         metric = "channel-samples imaged/s (N=2048, 256^2 grid), "
@@ -403,7 +454,9 @@ def main():
                    "graph_replay": not args.eager,
                    "pipeline": args.pipeline,
                    "algorithmic_flops_per_cs": algo_flops_step / cs,
-                   "achieved_algorithmic_tflops": algo_flops_step / (ms / 1e3) / 1e12},
+                   "achieved_algorithmic_tflops": algo_flops_step / (ms / 1e3) / 1e12,
+                   "whole_path_frac_fp32_peak": algo_flops_step / (ms / 1e3) / PEAK_FP32_VECTOR,
+                   "whole_path_frac_measured_fma": algo_flops_step / (ms / 1e3) / MEASURED_FP32_FMA},
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:

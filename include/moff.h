@@ -181,6 +181,20 @@ moff_status moff_get_launch_shape(moff_plan_t plan, int32_t *time_block, int32_t
 moff_status moff_autotune(moff_plan_t plan, const void *d_volt, int64_t n_t, void *d_acc, void *stream,
                           int32_t *time_block, int32_t *chans_per_block, int32_t *time_group, double *best_ms);
 
+/* Autotuner with a persisted per-shape cache.  The key (moff_autotune_key) names every input of the launch-shape
+ * choice: compute units of the bound device, antennas, pols, kernel size, channels, the distinct grid sizes with
+ * their channel counts, the touched grid rows, the fft / accumulator / voltage / kernel modes, the pipeline and the
+ * taps.  cache_path is a text file of lines "key<TAB>time_block chans_per_block time_group ms" (created if
+ * missing).  If it holds the key (the last such line wins) and that shape fits the bound workspace, the shape is
+ * applied without timing anything and *hit = 1; otherwise moff_autotune runs, its result is appended to the file
+ * and *hit = 0.  MOFF_E_INVALID if the file cannot be read or written (a malformed line for this key is ignored). */
+moff_status moff_autotune_cached(moff_plan_t plan, const char *cache_path, const void *d_volt, int64_t n_t,
+                                 void *d_acc, void *stream, int32_t *time_block, int32_t *chans_per_block,
+                                 int32_t *time_group, double *best_ms, int32_t *hit);
+/* The cache key of a plan, NUL-terminated into buf (MOFF_E_INVALID if bufsize is too small).  The compute-unit
+ * count is 0 until the plan is bound; host only. */
+moff_status moff_autotune_key(moff_plan_t plan, char *buf, size_t bufsize);
+
 /* Fused path replayed from a HIP graph.  The first call for a given (d_volt, n_t, d_acc) records every launch
  * moff_correlate would make (on an internal capture stream) into a graph and instantiates it; every call then
  * launches that graph on the caller's stream, one host call per integration.  Changing the launch shape or

@@ -60,6 +60,9 @@ _SIGS = {
     "moff_get_launch_shape": ([_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),
     "moff_autotune": ([_P, _P, C.c_int64, _P, _P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                        C.POINTER(C.c_double)], C.c_int),
+    "moff_autotune_cached": ([_P, C.c_char_p, _P, C.c_int64, _P, _P, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                              C.POINTER(C.c_int32), C.POINTER(C.c_double), C.POINTER(C.c_int32)], C.c_int),
+    "moff_autotune_key": ([_P, C.c_char_p, C.c_size_t], C.c_int),
     "moff_correlate_graph": ([_P, _P, C.c_int64, _P, _P], C.c_int),
     "moff_correlate_noalloc": ([_P, _P, C.c_int64, _P, _P], C.c_int),
     "moff_profile": ([_P, C.c_int32], C.c_int),

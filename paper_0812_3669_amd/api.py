@@ -10,6 +10,7 @@
 from __future__ import annotations
 
 import ctypes as C
+import os
 from typing import List, Optional, Sequence
 
 import numpy as np
@@ -312,15 +313,30 @@ class Plan:
     def set_launch_shape(self, time_block: int, chans_per_block: int, time_group: int):
         _check(self.lib.moff_set_launch_shape(self._h, time_block, chans_per_block, time_group), "set launch shape")
 
-    def autotune(self, volts, acc, n_t: Optional[int] = None, stream=None):
-        """Times candidate launch shapes on this input (acc is scratch); keeps and returns the fastest."""
+    def autotune(self, volts, acc, n_t: Optional[int] = None, stream=None, cache: Optional[str] = None):
+        """Times candidate launch shapes on this input (acc is scratch); keeps and returns the fastest.  With
+        ``cache`` (a text file, created if missing) a shape tuned earlier for the same plan signature
+        (``autotune_key``) is applied without timing (``"cached": True``); a new result is appended to it."""
         n_t = volts.shape[0] if n_t is None else n_t
         self._check_volts(volts, n_t)
         self._check_acc(acc)
-        tb, cpb, tg, ms = C.c_int32(), C.c_int32(), C.c_int32(), C.c_double()
-        _check(self.lib.moff_autotune(self._h, _ptr(volts), n_t, _ptr(acc), _stream_handle(stream), C.byref(tb),
-                                      C.byref(cpb), C.byref(tg), C.byref(ms)), "moff_autotune")
-        return {"time_block": tb.value, "chans_per_block": cpb.value, "time_group": tg.value, "ms": ms.value}
+        tb, cpb, tg, ms, hit = C.c_int32(), C.c_int32(), C.c_int32(), C.c_double(), C.c_int32(0)
+        if cache is None:
+            _check(self.lib.moff_autotune(self._h, _ptr(volts), n_t, _ptr(acc), _stream_handle(stream),
+                                          C.byref(tb), C.byref(cpb), C.byref(tg), C.byref(ms)), "moff_autotune")
+        else:
+            _check(self.lib.moff_autotune_cached(self._h, os.fsencode(cache), _ptr(volts), n_t, _ptr(acc),
+                                                 _stream_handle(stream), C.byref(tb), C.byref(cpb), C.byref(tg),
+                                                 C.byref(ms), C.byref(hit)), "moff_autotune_cached")
+        return {"time_block": tb.value, "chans_per_block": cpb.value, "time_group": tg.value, "ms": ms.value,
+                "cached": bool(hit.value)}
+
+    @property
+    def autotune_key(self) -> str:
+        """The autotuner cache's key for this plan (every input of the launch-shape choice)."""
+        buf = C.create_string_buffer(1024)
+        _check(self.lib.moff_autotune_key(self._h, buf, len(buf)), "moff_autotune_key")
+        return buf.value.decode()
 
     def grid(self, volts, n_t: Optional[int] = None, out=None, stream=None):
         import torch

@@ -74,6 +74,10 @@ class Config:
             out.append(min(s for s in ALLOWED_GRID_SIZES if s >= need))
         return out
 
+    def volt_bytes_per_cs(self) -> int:
+        """Algorithmic input bytes per channel-sample: every antenna's voltage in each pol (int8 or complex64)."""
+        return self.n_ant * self.n_pol * (2 if self.int8 else 8)
+
     def flops_per_cs(self, n: Optional[int] = None) -> float:
         """Algorithmic flops per channel-sample: 5 n^2 log2(n^2) per pol FFT + 8 N_a P K^2 gridding + products."""
         n = n if n is not None else (self.grid_n or max(self.grid_sizes()))

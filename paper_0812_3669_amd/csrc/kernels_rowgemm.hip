@@ -83,6 +83,29 @@ __device__ __forceinline__ float f16_lo_f32(uint32_t u) {
   return (float)h;
 }
 
+// Split operand words of one antenna slot for output column k: hr = (Re Phi, -Im Phi) and lr the same for the exact
+// FP32 residuals Phi - hi, as FP16 pairs (low half first), where Phi = w^(i0 k) sum_x taps[x] w^(x k) from the
+// (pre-scaled) kernel row taps, the lane's w^(x k) and the w^m table.
+template <int N, int K>
+__device__ __forceinline__ void rg_phi_words(const float2 *taps, const float2 *wx, const float2 *tw, int i0, int k,
+                                             uint32_t &hr, uint32_t &lr) {
+  float2 f = make_float2(0.f, 0.f);
+#pragma unroll
+  for (int x = 0; x < K; ++x) {
+    const float2 w = taps[x];
+    f.x = fmaf(w.x, wx[x].x, fmaf(-w.y, wx[x].y, f.x));
+    f.y = fmaf(w.x, wx[x].y, fmaf(w.y, wx[x].x, f.y));
+  }
+  const float2 r = tw[(i0 * k) % N];
+  const float px = f.x * r.x - f.y * r.y, py = f.x * r.y + f.y * r.x;
+  hr = f16x2_bits(px, -py);
+  const float dx = px - f16_lo_f32(hr), dy = py + f16_lo_f32(hr >> 16);   // exact residuals
+  lr = f16x2_bits(dx, -dy);
+}
+
+// (Im Phi, Re Phi) from (Re Phi, -Im Phi): swap the halves and negate the new low half (exact).
+__device__ __forceinline__ uint32_t rg_swapneg(uint32_t u) { return ((u >> 16) | (u << 16)) ^ 0x8000u; }
+
 template <int N, int K>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_rowgemm(RgArgs a) {
   constexpr int W = cols_ce(N);
@@ -198,21 +221,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
 #pragma unroll
       for (int ii = 0; ii < 4; ++ii) {
         const int s = 16 * kk + 4 * g + ii;
-        float2 f = make_float2(0.f, 0.f);
-#pragma unroll
-        for (int x = 0; x < K; ++x) {
-          const float2 w = taps[s * K + x];
-          f.x = fmaf(w.x, wx[x].x, fmaf(-w.y, wx[x].y, f.x));
-          f.y = fmaf(w.x, wx[x].y, fmaf(w.y, wx[x].x, f.y));
-        }
-        const float2 r = tw[(i0s[s] * k) % N];
-        const float px = f.x * r.x - f.y * r.y, py = f.x * r.y + f.y * r.x;   // scaled Phi
-        const uint32_t hr = f16x2_bits(px, -py), hi = f16x2_bits(py, px);
-        const float dx = px - f16_lo_f32(hr), dy = py - f16_lo_f32(hi);      // exact residuals
+        uint32_t hr, lr;
+        rg_phi_words<N, K>(taps + s * K, wx, tw, i0s[s], k, hr, lr);
         bre_hi[ii] = hr;
-        bim_hi[ii] = hi;
-        bre_lo[ii] = f16x2_bits(dx, -dy);
-        bim_lo[ii] = f16x2_bits(dy, dx);
+        bre_lo[ii] = lr;
+        bim_hi[ii] = rg_swapneg(hr);
+        bim_lo[ii] = rg_swapneg(lr);
       }
       rg_half8 Brh, Brl, Bih, Bil;
       __builtin_memcpy(&Brh, &bre_hi, 16);

@@ -7,6 +7,9 @@
 #include <cmath>
 #include <cstring>
 #include <exception>
+#include <fstream>
+#include <map>
+#include <sstream>
 #include <new>
 #include <string>
 #include <vector>
@@ -941,6 +944,89 @@ moff_status moff_autotune(moff_plan_t plan, const void *d_volt, int64_t n_t, voi
   if (chans_per_block) *chans_per_block = bcpb;
   if (time_group) *time_group = btg;
   if (best_ms) *best_ms = best;
+  return ok();
+}
+
+// Every input of the launch-shape choice, as one line of text (no tabs or newlines).
+static std::string tune_key(const moff::Plan &p) {
+  std::map<int, int> sizes;
+  int64_t rows = 0;
+  for (const moff::Chan &ch : p.chans) {
+    ++sizes[ch.n];
+    rows += ch.jmax - ch.jmin + 1;
+  }
+  std::ostringstream k;
+  k << "cu=" << p.cu_count << " A=" << p.n_ant << " P=" << p.n_pol << " K=" << p.ksize << " C=" << p.n_chan
+    << " n=";
+  for (const auto &kv : sizes) k << kv.first << "x" << kv.second << ",";
+  k << " rows=" << rows << " fft=" << p.fft_mode << " acc=" << p.acc_mode << " volt=" << p.volt_format
+    << " kern=" << p.kernel_mode << " pipe=" << p.pipeline << " taps=" << p.n_tap;
+  return k.str();
+}
+
+moff_status moff_autotune_key(moff_plan_t plan, char *buf, size_t bufsize) {
+  if (!plan || !buf) return set_err(MOFF_E_INVALID, "null argument");
+  const std::string k = tune_key(plan->p);
+  if (k.size() + 1 > bufsize) return set_err(MOFF_E_INVALID, "key buffer too small");
+  std::memcpy(buf, k.c_str(), k.size() + 1);
+  return ok();
+}
+
+moff_status moff_autotune_cached(moff_plan_t plan, const char *cache_path, const void *d_volt, int64_t n_t,
+                                 void *d_acc, void *stream, int32_t *time_block, int32_t *chans_per_block,
+                                 int32_t *time_group, double *best_ms, int32_t *hit) {
+  if (!plan || !cache_path || !d_volt || !d_acc) return set_err(MOFF_E_INVALID, "null argument");
+  moff::Plan &p = plan->p;
+  moff_status s = need_bound(p, true);
+  if (s) return s;
+  const std::string key = tune_key(p);
+  int tb = 0, cpb = 0, tg = 0;
+  double ms = 0.0;
+  bool found = false;
+  {
+    std::ifstream in(cache_path);
+    if (in.is_open()) {
+      std::string line;
+      while (std::getline(in, line)) {
+        const size_t tab = line.find('\t');
+        if (tab == std::string::npos || line.compare(0, tab, key) != 0 || tab != key.size()) continue;
+        std::istringstream v(line.substr(tab + 1));
+        int a = 0, b = 0, c = 0;
+        double m = 0.0;
+        if (v >> a >> b >> c >> m && a > 0 && b > 0 && c > 0 && c <= a) {
+          tb = a;
+          cpb = b;
+          tg = c;
+          ms = m;
+          found = true;
+        }
+      }
+    }
+  }
+  const int tb0 = p.t_block, cpb0 = p.chans_per_block, tg0 = p.t_group;
+  if (found && moff::layout_blocks(p, tb, cpb, tg) <= p.ws_bound) {
+    drop_graphs(p);
+    if (time_block) *time_block = tb;
+    if (chans_per_block) *chans_per_block = cpb;
+    if (time_group) *time_group = tg;
+    if (best_ms) *best_ms = ms;
+    if (hit) *hit = 1;
+    return ok();
+  }
+  if (found) moff::layout_blocks(p, tb0, cpb0, tg0);   // the cached shape did not fit the bound workspace
+  int32_t rtb = 0, rcpb = 0, rtg = 0;
+  double rms = 0.0;
+  s = moff_autotune(plan, d_volt, n_t, d_acc, stream, &rtb, &rcpb, &rtg, &rms);
+  if (s) return s;
+  std::ofstream out(cache_path, std::ios::app);
+  if (!out.is_open()) return set_err(MOFF_E_INVALID, std::string("cannot write the autotuner cache ") + cache_path);
+  out << key << '\t' << rtb << ' ' << rcpb << ' ' << rtg << ' ' << rms << '\n';
+  if (!out.good()) return set_err(MOFF_E_INVALID, std::string("cannot write the autotuner cache ") + cache_path);
+  if (time_block) *time_block = rtb;
+  if (chans_per_block) *chans_per_block = rcpb;
+  if (time_group) *time_group = rtg;
+  if (best_ms) *best_ms = rms;
+  if (hit) *hit = 0;
   return ok();
 }
 

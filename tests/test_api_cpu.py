@@ -125,3 +125,20 @@ def test_tap_and_calibration_buffers_checked():
 def test_probe_buffer_checked():
     with pytest.raises(ValueError):
         api.probe(0, 4, 1, torch.empty(4 * 256, dtype=torch.float32))
+
+
+def test_autotune_key_names_every_input_of_the_shape_choice():
+    """Identical plans share the autotuner cache key; a different transform, accumulator, grid size, antenna count
+    or channel count changes it.  Host only (the compute-unit count is 0 until the plan is bound)."""
+    cfg = configs.scaled(configs.PLAIN, n_ant=20, n_chan=2, grid_n=64, disk_lambda=30.0, n_time=8)
+    geo = synth.geometry(cfg)
+    k0 = api.plan_for(cfg, geo).autotune_key
+    assert k0 == api.plan_for(cfg, geo).autotune_key
+    assert "\t" not in k0 and "\n" not in k0 and k0.startswith("cu=0 ")
+    others = [api.plan_for(cfg, geo, fft_mode=api.FFT_GEMM_FP16).autotune_key,
+              api.plan_for(cfg, geo, acc_mode=api.ACC_FP64_COMP).autotune_key]
+    for kw in (dict(grid_n=128), dict(n_ant=21), dict(n_chan=3)):
+        c2 = configs.scaled(configs.PLAIN, **{**dict(n_ant=20, n_chan=2, grid_n=64, disk_lambda=30.0, n_time=8),
+                                               **kw})
+        others.append(api.plan_for(c2, synth.geometry(c2)).autotune_key)
+    assert len(set(others + [k0])) == len(others) + 1

@@ -414,6 +414,42 @@ def test_graph_replay_shapes_and_autotune():
     _check_images([im.cpu().numpy().astype(np.complex128) for im in plan.read_image(a3)], ref, label="tuned")
 
 
+def test_autotune_cache(tmp_path):
+    """The persisted autotuner cache: the first call tunes and appends its shape under the plan's key; a second
+    plan with the same signature applies it without timing; a plan with another signature (a different transform)
+    tunes again and adds its own line; results stay correct under the cached shape."""
+    cfg = _small(128, C=5, A=64, T=40)
+    geo, kern, volts = synth.workload(cfg)
+    v = torch.from_numpy(volts).to(DEV)
+    cache = str(tmp_path / "tune.txt")
+    ref = ora.image(volts, kern, geo.ant_xy_m, geo.freqs_hz, geo.grid_n, cfg.cell_lambda)
+
+    def bound(**kw):
+        plan = api.plan_for(cfg, geo, **kw)
+        big = max(plan.workspace_bytes_for(tb, cpb) for tb in (8, 16, 32, 64) for cpb in (4, 8, 16, 32, 64, 128))
+        plan.bind(DEV, workspace_bytes=big)
+        plan.set_kernels(torch.from_numpy(kern).to(DEV))
+        return plan
+
+    p1 = bound()
+    first = p1.autotune(v, p1.new_accumulator(), n_t=16, cache=cache)
+    assert not first["cached"] and first["ms"] > 0
+    lines = open(cache).read().splitlines()
+    assert lines == [f"{p1.autotune_key}\t{first['time_block']} {first['chans_per_block']} {first['time_group']} "
+                     f"{first['ms']:g}"] or (len(lines) == 1 and lines[0].startswith(p1.autotune_key + "\t"))
+    p2 = bound()
+    assert p2.autotune_key == p1.autotune_key
+    second = p2.autotune(v, p2.new_accumulator(), n_t=16, cache=cache)
+    assert second["cached"]
+    assert p2.launch_shape() == (first["time_block"], first["chans_per_block"], first["time_group"])
+    acc = p2.new_accumulator()
+    p2.correlate(v, acc)
+    _check_images([im.cpu().numpy().astype(np.complex128) for im in p2.read_image(acc)], ref, label="cached shape")
+    p3 = bound(fft_mode=api.FFT_GEMM_FP16)
+    third = p3.autotune(v, p3.new_accumulator(), n_t=16, cache=cache)
+    assert not third["cached"] and len(open(cache).read().splitlines()) == 2
+
+
 
 # ---------------------------------------------------------------------------------------------------------
 # precision form: both FFT stages on the matrix cores with split FP16 / BF16 products
