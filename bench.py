@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 PEAK_FP32_VECTOR = 157.3e12    # MI355X published FP32 vector peak (packed FP32), FLOP/s
 PEAK_HBM = 8.0e12              # MI355X HBM3E, B/s
 PEAK_MFMA_16 = 2.5e15          # MI355X published dense FP16 / BF16 matrix-core peak, FLOP/s
-# Ceilings measured on the box (profiles/peaks_probe.md, profiles/k_rows_k_cols_headline_fp32_traffic.md): the FP32
+# Ceilings measured on the box (profiles/peaks_probe.md, profiles/hbm_copy_calibration.md): the FP32
 # FMA issue rate of this build (packed FP32 disabled), the FP16 matrix-core instruction rate, and a plain 1 GiB
 # device copy (read + write).
 MEASURED_FP32_FMA = 119.5e12
@@ -421,14 +421,16 @@ def main():
         # what the kernel as built moves: the row-to-column exchange, far above the algorithmic bytes.  Its
         # arithmetic intensity against the ridge (peak flops / 8 TB/s) says which roof binds it.
         gbs = traffic / (avg_ms / 1e3)
+        peak = PEAK_MFMA_16 if d["mfma_flops"] > 0 else PEAK_FP32_VECTOR
         intensity = (d["mfma_flops"] if d["mfma_flops"] > 0 else d["flops"]) / nl / traffic
-        ridge = (PEAK_MFMA_16 if d["mfma_flops"] > 0 else PEAK_FP32_VECTOR) / PEAK_HBM
+        attainable = min(peak, intensity * PEAK_HBM)   # the roofline at the measured intensity
         roofline["limiter"] = {
             "measured_bytes_per_launch": traffic,
             "algorithmic_bytes_per_launch": launch_cs * cfg.volt_bytes_per_cs(),
             "achieved_gbs": gbs / 1e9, "frac_hbm_peak": gbs / PEAK_HBM, "frac_measured_copy": gbs / MEASURED_COPY,
-            "flop_per_byte": intensity, "ridge_flop_per_byte": ridge,
-            "binding_roof": "hbm" if intensity < ridge else roofline["bound"]}
+            "flop_per_byte": intensity, "ridge_flop_per_byte": peak / PEAK_HBM,
+            "lower_roof": "hbm" if intensity * PEAK_HBM < peak else roofline["bound"],
+            "attainable_tflops": attainable / 1e12, "frac_of_attainable": achieved / attainable}
     algo_flops_step = sum(T * cfg.flops_per_cs(n) for n in plan.grid_n)
     if args.workload == "headline":
         metric = "channel-samples imaged/s (N=2048, 256^2 grid), "
