@@ -292,6 +292,20 @@ def main():
             e1.record()
             e1.synchronize()
             res[name] = round(flops / (e0.elapsed_time(e1) * 1e-3) / 1e12, 1)
+        # the two exchanges between the stages of a 256-point transform: through LDS (radix-16 stages, the
+        # library's scheme) and across lanes (radix-2 stages with DPP / swizzle / permute), 2048 x 16 transforms
+        # of a random batch, 64 repeats per launch
+        data = torch.randn(2048 * 16 * 256, dtype=torch.complex64, device=dev)
+        for kind, name in ((2, "fft256_lds_exchange"), (3, "fft256_crosslane_exchange")):
+            api.probe(kind, 2048, 64, data)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            flops = sum(api.probe(kind, 2048, 64, data) for _ in range(10))
+            e1.record()
+            e1.synchronize()
+            sec = e0.elapsed_time(e1) * 1e-3
+            res[name] = {"tflops": round(flops / sec / 1e12, 1),
+                         "transforms_per_s": round(flops / (5 * 256 * 8) / sec / 1e9, 3) * 1e9}
         print(json.dumps(res))
         return
 

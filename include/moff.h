@@ -274,8 +274,14 @@ moff_status moff_profile_read(moff_plan_t plan, int32_t kind, double *total_ms, 
  * `iters` iterations of 8 independent FP32 FMA chains (blocks x 256 x iters x 16 flops); kind 1 runs `blocks`
  * workgroups of 4 wavefronts, each wavefront `iters` x 4 independent v_mfma_f32_16x16x32_f16 (blocks x 4 x iters
  * x 4 x 16384 flops).  d_out: caller-owned device float [blocks x 256], one value per thread (the work is not
- * optimised away).  Enqueues on `stream`; the caller times it.  MOFF_E_INVALID for blocks or iters < 1, a NULL
- * d_out or an unknown kind. */
+ * optimised away).
+ * Exchange probes (the data movement between the stages of a spatial transform, Eq. m6 step 3): d_out holds
+ * blocks x 16 complex float transforms of 256 points, transformed in place iters times, each time
+ * X[k] = (1/256) sum_n x[n] e^(+2 pi i n k / 256).  Kind 2: two radix-16 stages per transform with the transpose
+ * between them through LDS (natural-order output); kind 3: eight radix-2 stages, the last six exchanging values
+ * across the lanes of a wavefront (output position n holds X[bit-reversed n]).
+ * Enqueues on `stream`; the caller times it.  MOFF_E_INVALID for blocks or iters < 1, a NULL d_out or an unknown
+ * kind. */
 moff_status moff_probe(int32_t kind, int32_t blocks, int32_t iters, float *d_out, void *stream);
 
 void moff_plan_destroy(moff_plan_t plan);

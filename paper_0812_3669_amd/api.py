@@ -428,15 +428,26 @@ class Plan:
 
 
 def probe(kind: int, blocks: int, iters: int, out, stream=None):
-    """Enqueues an issue-rate probe (``moff_probe``): kind 0 FP32 vector FMAs, kind 1 FP16 matrix-core
-    instructions; ``out`` is a device float tensor of blocks x 256 elements.  Returns the flops it performs."""
+    """Enqueues a probe (``moff_probe``): kind 0 FP32 vector FMAs, kind 1 FP16 matrix-core instructions (``out`` a
+    device float32 tensor of blocks x 256 elements); kinds 2 and 3 the exchange probes, 256-point transforms with
+    an LDS transpose or cross-lane exchanges (``out`` a device complex64 tensor of blocks x 16 x 256 elements,
+    transformed in place).  Returns the flops it performs (5 N log2 N per transform for kinds 2 and 3)."""
     import torch
     lib = _lib.load()
     if not isinstance(out, torch.Tensor) or not out.is_cuda:
-        raise ValueError("out must be a device tensor of blocks x 256 floats")
-    _check_buffer(out, "out", out.device, torch.float32, blocks * 256 * 4)
+        raise ValueError("out must be a device tensor")
+    if kind in (0, 1):
+        _check_buffer(out, "out", out.device, torch.float32, blocks * 256 * 4)
+    elif kind in (2, 3):
+        _check_buffer(out, "out", out.device, torch.complex64, blocks * 16 * 256 * 8)
+    else:
+        raise ValueError(f"unknown probe kind {kind}")
     _check(lib.moff_probe(kind, blocks, iters, _ptr(out), _stream_handle(stream)), "probe")
-    return blocks * 256 * iters * 16 if kind == 0 else blocks * 4 * iters * 4 * 16384
+    if kind == 0:
+        return blocks * 256 * iters * 16
+    if kind == 1:
+        return blocks * 4 * iters * 4 * 16384
+    return blocks * 16 * iters * 5 * 256 * 8
 
 
 def plan_for(cfg, geo, **kw) -> "Plan":

@@ -5,6 +5,7 @@
 
 #include <cstdint>
 
+#include "fft_radix.h"
 #include "kernels.h"
 
 namespace moff {
@@ -54,11 +55,125 @@ __global__ __launch_bounds__(256) void k_probe_mfma(int iters, float *out) {
   out[(int64_t)blockIdx.x * blockDim.x + threadIdx.x] = s;
 }
 
+// Exchange probes: batches of 256-point transforms X[k] = (1/256) sum_n x[n] e^(2 pi i n k / 256) (the 1/256 keeps
+// the repeated transforms finite), computed two ways that differ in how data moves between stages.  Each
+// workgroup keeps its transforms in registers and transforms its own output iters times, then writes it back.
+//
+// kind 2, LDS exchange (the scheme of the library's FFT passes): 16 threads per transform, thread j holding
+// x[j + 16 m]; a radix-16 DFT over m in registers, the twiddle w256^(j k1), the 16 x 16 transpose through padded
+// LDS between two barriers, a radix-16 DFT over j; thread j ends with X[j + 16 k2] (natural order).
+__global__ __launch_bounds__(256) void k_probe_fft_lds(int iters, float2 *data) {
+  __shared__ float2 lds[16][16][17];   // [transform][k1][j], padded
+  const int tr = (int)threadIdx.x >> 4, j = (int)threadIdx.x & 15;
+  float2 *x = data + ((int64_t)blockIdx.x * 16 + tr) * 256;
+  float2 v[16], tw[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) v[m] = x[j + 16 * m];
+#pragma unroll
+  for (int k1 = 0; k1 < 16; ++k1) {
+    float sn, cs;
+    sincospif((float)(j * k1) / 128.f, &sn, &cs);
+    tw[k1] = make_float2(cs, sn);
+  }
+  for (int it = 0; it < iters; ++it) {
+    dft16(v);   // v[k1] = Y[j][k1]
+#pragma unroll
+    for (int k1 = 0; k1 < 16; ++k1) lds[tr][k1][j] = cmul(v[k1], tw[k1]);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = lds[tr][j][i];   // this thread now holds column k1 = j
+    __syncthreads();
+    dft16(v);   // v[k2] = X[j + 16 k2]
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] = cscale(v[k], 1.f / 256.f);
+  }
+#pragma unroll
+  for (int k = 0; k < 16; ++k) x[j + 16 * k] = v[k];
+}
+
+// Partner value of lane l ^ H within a wavefront: DPP quad permutes for H = 1, 2, the data-share swizzle (xor
+// mode, no LDS memory) for H = 4, 8, 16, a backward permute for H = 32.
+template <int H>
+__device__ __forceinline__ float xlane_xor(float v) {
+  const int i = __float_as_int(v);
+  int r;
+  if constexpr (H == 1)
+    r = __builtin_amdgcn_mov_dpp(i, 0xB1, 0xF, 0xF, false);   // quad_perm [1, 0, 3, 2]
+  else if constexpr (H == 2)
+    r = __builtin_amdgcn_mov_dpp(i, 0x4E, 0xF, 0xF, false);   // quad_perm [2, 3, 0, 1]
+  else if constexpr (H < 32)
+    r = __builtin_amdgcn_ds_swizzle(i, (H << 10) | 0x1F);      // and 0x1F, or 0, xor H
+  else
+    r = __builtin_amdgcn_ds_bpermute((int)((threadIdx.x & 63) ^ 32) << 2, i);
+  return __int_as_float(r);
+}
+
+// One radix-2 decimation-in-frequency stage of span H across lanes: the lower lane keeps a + b, the upper lane
+// (a - b) w_2H^(l mod H).
+template <int H>
+__device__ __forceinline__ void xlane_stage(float2 (&v)[4], int l, float2 w) {
+  const bool upper = (l & H) != 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const float2 p = make_float2(xlane_xor<H>(v[q].x), xlane_xor<H>(v[q].y));
+    v[q] = upper ? cmul(csub(p, v[q]), w) : cadd(v[q], p);
+  }
+}
+
+// kind 3, cross-lane exchange: 64 lanes per transform, lane l holding x[l + 64 q], q < 4; eight radix-2
+// decimation-in-frequency stages, the first two inside the lane, the last six exchanging partner values across
+// lanes (no LDS arrays, no barriers).  Position n ends with X[bitrev8(n)].
+__global__ __launch_bounds__(256) void k_probe_fft_xlane(int iters, float2 *data) {
+  const int l = (int)threadIdx.x & 63, tr = (int)threadIdx.x >> 6;
+  float2 *x = data + ((int64_t)blockIdx.x * 4 + tr) * 256;
+  float2 v[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) v[q] = x[l + 64 * q];
+  auto w_of = [](int t, int span) {   // e^(2 pi i t / span)
+    float sn, cs;
+    sincospif(2.f * (float)t / (float)span, &sn, &cs);
+    return make_float2(cs, sn);
+  };
+  const float2 w128a = w_of(l, 256), w128b = w_of(l + 64, 256), w64 = w_of(l, 128);
+  const float2 w32 = w_of(l & 31, 64), w16 = w_of(l & 15, 32), w8 = w_of(l & 7, 16), w4 = w_of(l & 3, 8),
+               w2 = w_of(l & 1, 4), w1 = make_float2(1.f, 0.f);
+  for (int it = 0; it < iters; ++it) {
+    {   // span 128: (q, q + 2)
+      const float2 a0 = v[0], b0 = v[2], a1 = v[1], b1 = v[3];
+      v[0] = cadd(a0, b0);
+      v[2] = cmul(csub(a0, b0), w128a);
+      v[1] = cadd(a1, b1);
+      v[3] = cmul(csub(a1, b1), w128b);
+    }
+    {   // span 64: (q, q + 1)
+      const float2 a0 = v[0], b0 = v[1], a1 = v[2], b1 = v[3];
+      v[0] = cadd(a0, b0);
+      v[1] = cmul(csub(a0, b0), w64);
+      v[2] = cadd(a1, b1);
+      v[3] = cmul(csub(a1, b1), w64);
+    }
+    xlane_stage<32>(v, l, w32);
+    xlane_stage<16>(v, l, w16);
+    xlane_stage<8>(v, l, w8);
+    xlane_stage<4>(v, l, w4);
+    xlane_stage<2>(v, l, w2);
+    xlane_stage<1>(v, l, w1);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = cscale(v[q], 1.f / 256.f);
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) x[l + 64 * q] = v[q];
+}
+
 hipError_t launch_probe(int kind, int blocks, int iters, float *out, hipStream_t st) {
   if (kind == 0)
     hipLaunchKernelGGL(k_probe_fma, dim3(blocks), dim3(256), 0, st, iters, out);
-  else
+  else if (kind == 1)
     hipLaunchKernelGGL(k_probe_mfma, dim3(blocks), dim3(256), 0, st, iters, out);
+  else if (kind == 2)
+    hipLaunchKernelGGL(k_probe_fft_lds, dim3(blocks), dim3(256), 0, st, iters, reinterpret_cast<float2 *>(out));
+  else
+    hipLaunchKernelGGL(k_probe_fft_xlane, dim3(blocks * 4), dim3(256), 0, st, iters, reinterpret_cast<float2 *>(out));
   return hipGetLastError();
 }
 

@@ -57,3 +57,30 @@ def test_mfma_probe_matches_the_tile_product():
     want1 = np.tile(per_lane, 4 * blocks)
     np.testing.assert_allclose(got1, want1, rtol=1e-5, atol=1e-9)
     np.testing.assert_allclose(got3, 3 * want1, rtol=1e-5, atol=1e-9)
+
+
+def _bitrev8(n):
+    return int(f"{n:08b}"[::-1], 2)
+
+
+@pytest.mark.parametrize("kind", [2, 3])
+def test_exchange_probes_transform(kind):
+    """Both exchange probes compute X[k] = (1/256) sum_n x[n] e^(+2 pi i n k / 256) (numpy's inverse FFT): kind 2 in
+    natural order, kind 3 with position n holding X[bitrev8(n)]; one and two repeats (the second transforms the
+    first's output as it lies in memory)."""
+    blocks = 3
+    rng = np.random.default_rng(kind)
+    x = (rng.standard_normal((blocks * 16, 256)) + 1j * rng.standard_normal((blocks * 16, 256))).astype(np.complex64)
+    perm = np.arange(256) if kind == 2 else np.array([_bitrev8(n) for n in range(256)])
+    for iters in (1, 2):
+        d = torch.from_numpy(x.ravel()).to(DEV)
+        print(f"exchange probe kind={kind} blocks={blocks} iters={iters}", flush=True)
+        flops = api.probe(kind, blocks, iters, d)
+        torch.cuda.synchronize()
+        assert flops == blocks * 16 * iters * 5 * 256 * 8
+        want = x.astype(np.complex128)
+        for _ in range(iters):
+            want = np.fft.ifft(want, axis=1)[:, perm]
+        got = d.cpu().numpy().reshape(blocks * 16, 256)
+        err = np.abs(got - want).max() / np.abs(want).max()
+        assert err < 1e-5, (kind, iters, err)
