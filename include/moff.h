@@ -280,6 +280,8 @@ moff_status moff_profile_read(moff_plan_t plan, int32_t kind, double *total_ms, 
  * X[k] = (1/256) sum_n x[n] e^(+2 pi i n k / 256).  Kind 2: two radix-16 stages per transform with the transpose
  * between them through LDS (natural-order output); kind 3: eight radix-2 stages, the last six exchanging values
  * across the lanes of a wavefront (output position n holds X[bit-reversed n]).
+ * Kind 4: thread 0 of each of `blocks` workgroups writes its XCD number (hardware XCC_ID) to d_out[b] (float
+ * [blocks]; iters unused but >= 1).
  * Enqueues on `stream`; the caller times it.  MOFF_E_INVALID for blocks or iters < 1, a NULL d_out or an unknown
  * kind. */
 moff_status moff_probe(int32_t kind, int32_t blocks, int32_t iters, float *d_out, void *stream);

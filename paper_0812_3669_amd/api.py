@@ -440,6 +440,8 @@ def probe(kind: int, blocks: int, iters: int, out, stream=None):
         _check_buffer(out, "out", out.device, torch.float32, blocks * 256 * 4)
     elif kind in (2, 3):
         _check_buffer(out, "out", out.device, torch.complex64, blocks * 16 * 256 * 8)
+    elif kind == 4:
+        _check_buffer(out, "out", out.device, torch.float32, blocks * 4)
     else:
         raise ValueError(f"unknown probe kind {kind}")
     _check(lib.moff_probe(kind, blocks, iters, _ptr(out), _stream_handle(stream)), "probe")
@@ -447,6 +449,8 @@ def probe(kind: int, blocks: int, iters: int, out, stream=None):
         return blocks * 256 * iters * 16
     if kind == 1:
         return blocks * 4 * iters * 4 * 16384
+    if kind == 4:
+        return 0
     return blocks * 16 * iters * 5 * 256 * 8
 
 

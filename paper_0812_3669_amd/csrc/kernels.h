@@ -108,6 +108,12 @@ inline int cols_xcd_grid(const Block &b, int groups) {
 
 typedef float vfloat2 __attribute__((ext_vector_type(2)));
 
+// The XCD (accelerator complex die) this wave runs on: hardware register XCC_ID (id 20), bits 3:0.  Workgroups
+// on one XCD share its L2.
+__device__ __forceinline__ int xcc_id() {
+  return (int)(__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 0xFu);   // size 4, offset 0, register 20
+}
+
 // Streaming store / load of the row-transform buffer: written once, read once, kept out of the way of the
 // tap tables in L2.
 __device__ __forceinline__ void store_stream(float2 *p, float2 v) {

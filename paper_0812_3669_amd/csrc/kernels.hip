@@ -684,18 +684,21 @@ void k_cols(ColArgs a) {
 // ------------------------------------------------------------------------------------------------------------
 // Streaming form of the fused path: one persistent launch per grid size.
 //
-// Team x (workgroups b with b % 8 == x, which the dispatcher places on XCD x, so a channel's tap tables stay in
-// one L2) processes channels c0 + x + 8 k, their samples in order.  The first G = N / W workgroups of a team own
-// one column group each (column FFTs, products, accumulator update every t_block samples, exactly as k_cols);
-// the others are row workers taking (sample, band) tasks in sample order (exactly k_rows for one sample).
-// Row-transformed samples pass through a ring of S slots per team.  The ring is written and read with
-// device-coherent accesses (they bypass the non-coherent caches and meet at the memory side, where the MALL
-// holds the small ring), so correctness does not depend on where a workgroup runs.  Per slot, two cumulative
-// counters: bands produced and column groups consumed.  A row task for sample u waits until every owner has
-// consumed sample u - S; an owner waits until every band of its sample has been produced.  Producers make their
-// stores complete (vmcnt 0) before the counter increment.  Every wait is bounded: past the spin limit, or once
-// any workgroup has flagged an error, it sets the error flag and returns, so the launch always ends.  The launch
-// needs all its workgroups resident at once: the host sizes it from the occupancy.
+// Teams are the workgroups that share one XCD: at start every workgroup reads the XCD it runs on (hardware
+// XCC_ID), takes the next rank on that XCD (a device-scope counter) and waits until every workgroup of the launch
+// has registered.  Team x processes channels c0 + x + 8 k, their samples in order.  Ranks below G = N / W own one
+// column group each (column FFTs, products, accumulator update every t_block samples, exactly as k_cols); the
+// others are row workers taking (sample, band) tasks in sample order (exactly k_rows for one sample).
+// Row-transformed samples pass through a ring of S slots per team, written and read with device-coherent
+// accesses (they bypass the non-coherent caches and meet at the memory side, where the MALL holds the small
+// ring).  A team's L2 alone cannot carry it: plain loads may hit lines of an earlier use of the slot left in the
+// CU's L1, and no instruction invalidates only the L1 when a workgroup runs on one CU.  Per slot, two cumulative
+// device-scope counters: bands produced and column groups consumed.  A row task for sample u waits until every owner has consumed sample u - S; an owner
+// waits until every band of its sample has been produced.  Producers make their stores complete (vmcnt 0) before
+// the counter increment.  Every wait is bounded: past the spin limit, or once any workgroup has flagged an
+// error, it sets the error flag and returns, so the launch always ends (an XCD with fewer than G + 1
+// workgroups flags error 2).  The launch needs all its workgroups resident at once: the host sizes it from the
+// occupancy.
 // ------------------------------------------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t ctr_load(const uint32_t *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -786,13 +789,34 @@ template <int N, int P, int W, int ACC, bool KJ>
 __global__ __launch_bounds__(kThreads) void k_stream(StreamArgs s) {
   constexpr int G = N / W;
   extern __shared__ float4 smem4[];
-  float2 *tws = reinterpret_cast<float2 *>(smem4);   // [2N] twiddle tables
-  float2 *work = tws + 2 * N;                        // row band grid or column buffer
-  const int x = (int)(blockIdx.x % kXcds), w = (int)(blockIdx.x / kXcds);
+  int *team = reinterpret_cast<int *>(smem4);            // XCD, rank on it, workgroups on it
+  float2 *tws = reinterpret_cast<float2 *>(smem4 + 1);   // [2N] twiddle tables
+  float2 *work = tws + 2 * N;                            // row band grid or column buffer
+  if (threadIdx.x == 0) {
+    uint32_t *reg = s.ctr + kStreamRegWord, *arrived = reg + kXcds;
+    const int xcc = xcc_id();
+    const uint32_t rank = __hip_atomic_fetch_add(reg + xcc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(arrived, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t spins = 0;
+    while (ctr_load(arrived) < gridDim.x) {
+      if (__hip_atomic_load(s.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+      if (++spins > s.spin_limit) {
+        __hip_atomic_store(s.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(8);
+    }
+    team[0] = xcc;
+    team[1] = (int)rank;
+    team[2] = (int)ctr_load(reg + xcc);
+    if (team[2] <= G) __hip_atomic_store(s.err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
   for (int i = threadIdx.x; i < 2 * N; i += kThreads) tws[i] = s.r.tw[i];
   __syncthreads();
+  const int x = team[0], w = team[1];
+  if (__hip_atomic_load(s.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
   const int nch = x < s.n_chan_group ? (s.n_chan_group - x + kXcds - 1) / kXcds : 0;
-  const int R = s.wgs_per_xcd - G;
+  const int R = team[2] - G;
   for (int k = 0; k < nch; ++k) {
     if (w < G)
       stream_owner<N, P, W, ACC>(s, x, w, k, work, tws);
@@ -1083,7 +1107,7 @@ size_t stream_lds_bytes(int n, int P, int band_ants, int volt_fmt) {
   const size_t rows = (size_t)P * band_rows_ce(n, P) * row_stride(n) * 8 +
                       (row_stages_volts(n) ? volt_table_bytes(band_ants, P, volt_fmt) : 0);
   const size_t cols = cols_lds_bytes(n, P, cols_ce(n)) - (size_t)2 * n * 8;
-  return (size_t)2 * n * 8 + (rows > cols ? rows : cols);
+  return 16 + (size_t)2 * n * 8 + (rows > cols ? rows : cols);   // team record, twiddles, work area
 }
 
 hipError_t stream_occupancy(int n, int P, int accm, bool jones, int band_ants, int volt_fmt, int *wgs_per_cu) {

@@ -165,6 +165,12 @@ __global__ __launch_bounds__(256) void k_probe_fft_xlane(int iters, float2 *data
   for (int q = 0; q < 4; ++q) x[l + 64 * q] = v[q];
 }
 
+// XCD of each workgroup (kind 4): the hardware register XCC_ID (bits 3:0), as the streaming form reads it to form
+// its per-XCD teams; thread 0 of workgroup b writes it to out[b].
+__global__ __launch_bounds__(256) void k_probe_xcc(float *out) {
+  if (threadIdx.x == 0) out[blockIdx.x] = (float)xcc_id();
+}
+
 hipError_t launch_probe(int kind, int blocks, int iters, float *out, hipStream_t st) {
   if (kind == 0)
     hipLaunchKernelGGL(k_probe_fma, dim3(blocks), dim3(256), 0, st, iters, out);
@@ -172,8 +178,10 @@ hipError_t launch_probe(int kind, int blocks, int iters, float *out, hipStream_t
     hipLaunchKernelGGL(k_probe_mfma, dim3(blocks), dim3(256), 0, st, iters, out);
   else if (kind == 2)
     hipLaunchKernelGGL(k_probe_fft_lds, dim3(blocks), dim3(256), 0, st, iters, reinterpret_cast<float2 *>(out));
-  else
+  else if (kind == 3)
     hipLaunchKernelGGL(k_probe_fft_xlane, dim3(blocks * 4), dim3(256), 0, st, iters, reinterpret_cast<float2 *>(out));
+  else
+    hipLaunchKernelGGL(k_probe_xcc, dim3(blocks), dim3(256), 0, st, out);
   return hipGetLastError();
 }
 

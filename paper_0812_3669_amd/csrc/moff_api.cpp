@@ -161,7 +161,7 @@ moff_status enqueue_stream(moff::Plan &p, const void *d_volt, int64_t n_t, void 
   uint32_t *ctr = reinterpret_cast<uint32_t *>(ws(p, p.ws_ctr));
   s.ring = reinterpret_cast<float2 *>(ws(p, p.ws_ring));
   s.ctr = ctr;
-  s.err = reinterpret_cast<int *>(ctr + (size_t)moff::kStreamXcds * 2 * moff::kStreamMaxSlots);
+  s.err = reinterpret_cast<int *>(ctr + moff::kStreamErrWord);
   s.slots = p.stream_slots;
   s.spin_limit = p.spin_limit;
   HIP_TRY(moff::launch_fill_zero(ctr, moff::kStreamCtrBytes, st), "clear stream counters");
@@ -181,9 +181,10 @@ moff_status enqueue_stream(moff::Plan &p, const void *d_volt, int64_t n_t, void 
       c0 = c1;
       continue;
     }
-    if (c0 > 0)
-      HIP_TRY(moff::launch_fill_zero(ctr, (size_t)moff::kStreamXcds * 2 * moff::kStreamMaxSlots * 4, st),
-              "clear stream counters");
+    if (c0 > 0) {   // slot counters and team registration for this launch (the error flag stays)
+      HIP_TRY(moff::launch_fill_zero(ctr, moff::kStreamCtrWords * 4, st), "clear stream counters");
+      HIP_TRY(moff::launch_fill_zero(ctr + moff::kStreamRegWord, 48, st), "clear stream counters");
+    }
     s.r.c0 = s.c.c0 = c0;
     s.r.tw = s.c.tw = d_tw(p, n);
     s.n_chan_group = c1 - c0;
@@ -371,7 +372,7 @@ void drop_graphs(moff::Plan &p) {
 extern "C" {
 
 moff_status moff_probe(int32_t kind, int32_t blocks, int32_t iters, float *d_out, void *stream) {
-  if (kind < 0 || kind > 3 || blocks < 1 || iters < 1 || !d_out)
+  if (kind < 0 || kind > 4 || blocks < 1 || iters < 1 || !d_out)
     return set_err(MOFF_E_INVALID, "bad probe arguments");
   HIP_TRY(moff::launch_probe(kind, blocks, iters, d_out, static_cast<hipStream_t>(stream)), "probe");
   return MOFF_OK;
@@ -878,7 +879,7 @@ moff_status moff_stream_status(moff_plan_t plan, int32_t *code) {
   if (s) return s;
   HIP_TRY(hipDeviceSynchronize(), "synchronize");
   const uint32_t *ctr = reinterpret_cast<const uint32_t *>(ws(p, p.ws_ctr));
-  HIP_TRY(hipMemcpy(code, ctr + (size_t)moff::kStreamXcds * 2 * moff::kStreamMaxSlots, 4, hipMemcpyDeviceToHost),
+  HIP_TRY(hipMemcpy(code, ctr + moff::kStreamErrWord, 4, hipMemcpyDeviceToHost),
           "read stream status");
   return ok();
 }

@@ -12,8 +12,11 @@ namespace moff {
 
 constexpr int kStreamXcds = 8;          // XCDs of the device (workgroup b runs on XCD b % 8)
 constexpr int kStreamMaxSlots = 8;
-// counters [kStreamXcds][2][kStreamMaxSlots] uint32, then the error flag (16 bytes)
-constexpr size_t kStreamCtrBytes = (size_t)kStreamXcds * 2 * kStreamMaxSlots * 4 + 16;
+// counters [kStreamXcds][2][kStreamMaxSlots] uint32, then the error flag (16 bytes), then the team registration:
+// workgroups per XCD [kStreamXcds] and the number registered (48 bytes)
+constexpr size_t kStreamCtrWords = (size_t)kStreamXcds * 2 * kStreamMaxSlots;
+constexpr size_t kStreamErrWord = kStreamCtrWords, kStreamRegWord = kStreamCtrWords + 4;
+constexpr size_t kStreamCtrBytes = (kStreamCtrWords + 16) * 4;
 
 constexpr int kThreads = 256;         // threads per workgroup of every hot-path kernel
 constexpr int kWaves = kThreads / 64;  // wavefronts per workgroup (64-wide on CDNA)

@@ -84,3 +84,16 @@ def test_exchange_probes_transform(kind):
         got = d.cpu().numpy().reshape(blocks * 16, 256)
         err = np.abs(got - want).max() / np.abs(want).max()
         assert err < 1e-5, (kind, iters, err)
+
+
+def test_xcd_ids():
+    """Every workgroup reads an XCD number in [0, 8) and all eight XCDs appear; printed beside b % 8, the
+    dispatcher's round-robin placement that the fused passes' channel-to-XCD mapping assumes."""
+    blocks = 4096
+    out = torch.full((blocks,), -1.0, dtype=torch.float32, device=DEV)
+    api.probe(4, blocks, 1, out)
+    torch.cuda.synchronize()
+    x = out.cpu().numpy().astype(int)
+    assert x.min() >= 0 and x.max() < 8 and len(set(x.tolist())) == 8
+    same = float(np.mean(x == (np.arange(blocks) % 8)))
+    print(f"XCD ids: counts {np.bincount(x, minlength=8).tolist()}, equal to b % 8 for {same:.3f} of workgroups")
