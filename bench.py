@@ -189,7 +189,7 @@ def serving_bench(args, dev):
         torch.cuda.synchronize()
         summ = st.summary()
         summ.update({"arrival_rate_jobs_per_s": rate, "hbm_budget_bytes": budget, "trace_seed": seed,
-                     "errors": st.errors})
+                     "errors": st.errors, "plans_built": ex.plans_built, "plans_reused": ex.plans_reused})
         mean_cs = float(np.mean([j.channel_samples for j in trace]))
         return summ, mean_cs
 

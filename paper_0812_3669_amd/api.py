@@ -149,6 +149,15 @@ class Plan:
         self.device = self._ws.device
         return self
 
+    def unbind(self):
+        """Releases the device workspace.  The plan keeps its host state (footprints, bands, tap groups, row lists)
+        and can be bound again, after which its kernels must be set again; until then every call that needs the
+        device raises (the buffer checks find no bound device)."""
+        self._ws = None
+        self._kern_ref = None
+        self.device = None
+        return self
+
     def _kernel_shape(self):
         if self.kernel_mode == KERNEL_JONES:
             return (self.n_chan, self.n_ant, 2, 2, self.ksize, self.ksize)

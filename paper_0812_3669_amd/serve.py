@@ -361,11 +361,13 @@ class GpuExecutor:
 
     A job's host set-up (its instrument's kernels, cached per array shape, and its plan) starts on a worker
     thread when it arrives, so it overlaps the device work of the jobs already running (numpy and the plan
-    builder release the interpreter lock).  Admission uses the exact device footprint of the built plan:
-    workspace + accumulator + image + kernels + one block of voltages.
+    builder release the interpreter lock).  Plans are reused: when a job ends its plan is unbound (its device
+    workspace freed) and kept, at most ``idle_per_shape`` per job shape (antennas, channels, grid, arithmetic form,
+    launch shape), for the next job of that shape, which then skips the plan build.  Admission uses the exact
+    device footprint of the built plan: workspace + accumulator + image + kernels + one block of voltages.
     """
 
-    def __init__(self, device="cuda:0", workers: int = 8):
+    def __init__(self, device="cuda:0", workers: int = 8, idle_per_shape: int = 2):
         import threading
         import torch
         from concurrent.futures import ThreadPoolExecutor
@@ -376,6 +378,10 @@ class GpuExecutor:
         self._plans = {}          # job id -> future of the plan
         self._sites = {}          # array shape -> future of the instrument (geometry, gains, kernels)
         self._site_dev = {}       # array shape -> [device kernels, active users]
+        self._idle = {}           # plan key -> unbound plans of finished jobs
+        self.idle_per_shape = idle_per_shape
+        self.plans_built = 0
+        self.plans_reused = 0
 
     def now(self):
         return time.perf_counter()
@@ -411,17 +417,40 @@ class GpuExecutor:
                 fut.set_exception(e)
         return fut.result()
 
+    @staticmethod
+    def _plan_key(spec, block):
+        return (spec.n_ant, spec.n_chan, spec.grid_n, spec.fft_mode, block, spec.chans_per_launch(block))
+
     def _prepare(self, spec, block):
         from . import api
+        key = self._plan_key(spec, block)
+        with self._lock:
+            idle = self._idle.get(key)
+            if idle:
+                self.plans_reused += 1
+                return idle.pop()
         site = self._site(spec)
         fft = {"fp32": api.FFT_FP32, "split_fp16": api.FFT_GEMM_FP16}[spec.fft_mode]
-        return api.plan_for(spec.site_config(), site["geo"], fft_mode=fft, time_block=block,
+        plan = api.plan_for(spec.site_config(), site["geo"], fft_mode=fft, time_block=block,
                             chans_per_block=spec.chans_per_launch(block))
+        with self._lock:
+            self.plans_built += 1
+        return plan
+
+    def _keep(self, spec, block, plan):
+        """An unbound plan back to the idle pool of its job shape (dropped beyond idle_per_shape)."""
+        plan.unbind()
+        with self._lock:
+            idle = self._idle.setdefault(self._plan_key(spec, block), [])
+            if len(idle) < self.idle_per_shape:
+                idle.append(plan)
 
     def prefetch(self, spec, block):
         with self._lock:
             if spec.job_id not in self._plans:
-                self._plans[spec.job_id] = self._pool.submit(self._prepare, spec, block)
+                fut = self._pool.submit(self._prepare, spec, block)
+                fut.block = block
+                self._plans[spec.job_id] = fut
 
     def ready(self, spec):
         fut = self._plans.get(spec.job_id)
@@ -440,7 +469,9 @@ class GpuExecutor:
         return int(plan.workspace_bytes + plan.acc_bytes + plan.image_bytes + kern + volt)
 
     def discard(self, spec):
-        self._plans.pop(spec.job_id, None)
+        fut = self._plans.pop(spec.job_id, None)
+        if fut is not None and fut.done() and fut.exception() is None:
+            self._keep(spec, getattr(fut, "block", 64), fut.result())
 
     def start(self, spec, block):
         from . import synth
@@ -501,6 +532,7 @@ class GpuExecutor:
             if dev[1] == 0:
                 del self._site_dev[h["site_key"]]   # free the device copy; the host copy stays cached
         self._plans.pop(h["spec"].job_id, None)
+        self._keep(h["spec"], h["block"], h["plan"])   # the job's stream is synchronised: nothing uses it now
 
     def finish(self, h):
         torch = self.torch

@@ -142,3 +142,17 @@ def test_autotune_key_names_every_input_of_the_shape_choice():
                                                **kw})
         others.append(api.plan_for(c2, synth.geometry(c2)).autotune_key)
     assert len(set(others + [k0])) == len(others) + 1
+
+
+def test_unbind_releases_the_device_and_blocks_calls():
+    """An unbound plan (its workspace released for reuse by a later job) refuses every device call until it is
+    bound again; its host-side queries still work."""
+    cfg, plan = _plan()
+    ws = plan.workspace_bytes
+    plan.unbind()
+    assert plan.device is None and plan.workspace_bytes == ws
+    with pytest.raises(ValueError, match="not bound"):
+        plan.correlate(_volts(cfg, 4), _acc(plan))
+    with pytest.raises(ValueError, match="not bound"):
+        plan.set_kernels(torch.empty((cfg.n_chan, cfg.n_ant, cfg.n_pol, cfg.ksize, cfg.ksize),
+                                     dtype=torch.complex64, device=META))

@@ -91,3 +91,18 @@ def test_failed_job_does_not_stop_the_others():
     assert s["failed"] == 1 and 99 in st.errors and s["jobs_completed"] == len(JOBS), (s, st.errors)
     alone = _run([JOBS[0]], 1)
     assert torch.equal(alone.results[0].cpu(), st.results[0].cpu())
+
+
+def test_plans_reused_across_jobs_of_one_shape():
+    """Jobs of one shape run one after another reuse the first job's plan (unbound when it ends, bound again for
+    the next): one plan built for three jobs, and each image equals the one a fresh executor computes alone."""
+    same = [serve.JobSpec(20 + k, 0.0, 256, 16, 64 + 16 * k, 128, "fp32", seed=30 + k) for k in range(3)]
+    ex = serve.GpuExecutor(DEV)
+    got = {}
+    for j in same:
+        st = _run([j], 1, ex)
+        got[j.job_id] = st.results[j.job_id].cpu()
+    assert ex.plans_built == 1 and ex.plans_reused == 2, (ex.plans_built, ex.plans_reused)
+    for j in same:
+        fresh = _run([j], 1)
+        assert torch.equal(fresh.results[j.job_id].cpu(), got[j.job_id]), j
