@@ -594,10 +594,10 @@ def test_jones_staged_grid_and_phase():
             assert err < 1e-6, (c, p, err)
 
 
-def test_batched_workload_three_channels():
+def test_batched_workload_every_grid_size():
     """The batching workload at full size (4096 antennas, 256 channels over 50-200 MHz, per-channel grids,
-    6x6 kernels) for 256 device-drawn samples through one graph-replayed correlate; the lowest, a middle and
-    the highest channel (smallest, middle and largest grid) checked pixel by pixel against the oracle."""
+    6x6 kernels) for 256 device-drawn samples through one graph-replayed correlate; the first channel of every
+    distinct grid size (128^2 .. 384^2) and the highest channel checked pixel by pixel against the oracle."""
     cfg = configs.scaled(configs.BATCHED, n_time=256)
     geo = synth.geometry(cfg)
     g = synth.gains(cfg)
@@ -611,9 +611,9 @@ def test_batched_workload_three_channels():
     plan.correlate_graph(volts, acc)
     imgs = plan.read_image(acc)
     sizes = plan.grid_n
-    mid = min(range(cfg.n_chan), key=lambda c: abs(sizes[c] - sorted(set(sizes))[len(set(sizes)) // 2]))
-    sel = [0, mid, cfg.n_chan - 1]
-    assert sizes[0] < sizes[mid] < sizes[-1], (sizes[0], sizes[mid], sizes[-1])
+    sel = sorted({sizes.index(n) for n in set(sizes)} | {cfg.n_chan - 1})
+    assert len(set(sizes)) == 6, sorted(set(sizes))
+    print(f"batched: channels {sel}, grids {[sizes[c] for c in sel]}", flush=True)
     v = volts[:, sel].cpu().numpy()
     ref = ora.image(v, kern[sel], geo.ant_xy_m, geo.freqs_hz[sel], geo.grid_n[sel], cfg.cell_lambda)
     _check_images([imgs[c].cpu().numpy().astype(np.complex128) for c in sel], ref, label="batched")
