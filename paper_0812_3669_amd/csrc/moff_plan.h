@@ -10,7 +10,7 @@
 
 namespace moff {
 
-constexpr int kStreamXcds = 8;          // XCDs of the device (workgroup b runs on XCD b % 8)
+constexpr int kStreamXcds = 8;          // XCDs of the device (the dispatcher places workgroup b on XCD b % 8)
 constexpr int kStreamMaxSlots = 8;
 // counters [kStreamXcds][2][kStreamMaxSlots] uint32, then the error flag (16 bytes), then the team registration:
 // workgroups per XCD [kStreamXcds] and the number registered (48 bytes)
