@@ -448,6 +448,19 @@ def test_autotune_cache(tmp_path):
     p3 = bound(fft_mode=api.FFT_GEMM_FP16)
     third = p3.autotune(v, p3.new_accumulator(), n_t=16, cache=cache)
     assert not third["cached"] and len(open(cache).read().splitlines()) == 2
+    # a malformed line and a shape that does not fit the bound workspace are not applied: the plan tunes again,
+    # keeps a shape that fits, and appends it (the last line for a key wins)
+    p4 = bound()
+    with open(cache, "a") as fh:
+        fh.write(f"{p4.autotune_key}\tnot numbers\n")
+        fh.write(f"{p4.autotune_key}\t4096 4096 64 0.1\n")
+    fourth = p4.autotune(v, p4.new_accumulator(), n_t=16, cache=cache)
+    assert not fourth["cached"]
+    assert p4.launch_shape() == (fourth["time_block"], fourth["chans_per_block"], fourth["time_group"])
+    assert open(cache).read().splitlines()[-1].startswith(p4.autotune_key + "\t")
+    p5 = bound()
+    fifth = p5.autotune(v, p5.new_accumulator(), n_t=16, cache=cache)
+    assert fifth["cached"] and p5.launch_shape() == p4.launch_shape()
 
 
 
