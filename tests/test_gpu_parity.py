@@ -302,6 +302,22 @@ def test_single_antenna_and_stacked_antennas():
         _check_images(imgs, ref, label=f"{xy.shape[0]} antennas")
 
 
+@pytest.mark.parametrize("n,K,fft", [(256, 4, api.FFT_FP32), (512, 4, api.FFT_FP32), (512, 8, api.FFT_FP32),
+                                     (512, 4, api.FFT_GEMM_FP16)])
+def test_maximum_antenna_count(n, K, fft):
+    """65534 antennas (the largest count a plan takes: tap metadata and row lists hold 16-bit antenna fields) in a
+    disk of 0.6 n cells: thousands of antennas per row band, tens of taps on each cell, band voltage tables of
+    several thousand records and (matrix-core form) about 70 K chunks per row."""
+    cfg = configs.scaled(configs.PLAIN, index=900 + n + K, n_ant=65534, n_pol=2, n_chan=1, n_time=3, ksize=K,
+                         grid_n=n, disk_lambda=0.6 * n, int8=True)
+    geo, kern, volts = synth.workload(cfg)
+    plan = api.plan_for(cfg, geo, fft_mode=fft).bind(DEV)
+    plan.set_kernels(torch.from_numpy(kern).to(DEV))
+    imgs, _ = _run_fused(plan, volts)
+    ref = ora.image(volts, kern, geo.ant_xy_m, geo.freqs_hz, geo.grid_n, cfg.cell_lambda)
+    _check_images(imgs, ref, label=f"65534 antennas n={n} K={K} fft={fft}", report=True)
+
+
 def test_deterministic_and_split_integration():
     """Same input twice -> bit-identical accumulators; an integration split at a time-block boundary equals
     the unsplit one bit for bit (accumulation is linear in time: checkpoint and resume)."""

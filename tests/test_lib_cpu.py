@@ -95,6 +95,23 @@ def test_plan_validation(kw, status):
     assert ei.value.status == status
 
 
+def test_antenna_count_limits():
+    """Antenna fields are 16 bits wide: 65534 antennas plan, 65535 do not; the matrix-core row pass rejects rows
+    whose antenna lists outgrow its LDS (MOFF_E_UNSUPPORTED) instead of launching them."""
+    rng = np.random.default_rng(5)
+    r = 0.3 * 256 * np.sqrt(rng.random(65535))
+    phi = 2 * np.pi * rng.random(65535)
+    xy = np.stack([r * np.cos(phi), r * np.sin(phi)], axis=1)
+    args = dict(freqs_hz=[configs.C_LIGHT], grid_n=[256], n_pol=2, ksize=4)
+    Plan(ant_xy_m=xy[:65534], **args)
+    with pytest.raises(MoffError) as ei:
+        Plan(ant_xy_m=xy, **args)
+    assert ei.value.status == 1
+    with pytest.raises(MoffError) as ei:
+        Plan(ant_xy_m=xy[:65534], fft_mode=3, **args)
+    assert ei.value.status == 4
+
+
 def test_footprint_outside_grid_is_invalid():
     xy = np.array([[14.0, 0.0]])     # X = 30 on a 32 grid: footprint 29..32 leaves the grid
     with pytest.raises(MoffError) as ei:
