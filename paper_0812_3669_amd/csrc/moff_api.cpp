@@ -611,12 +611,15 @@ moff_status moff_fft(moff_plan_t plan, void *d_grid, int64_t n_t, void *stream) 
     const size_t lds = moff::rows_lds_bytes(b.n, p.n_pol, p.chans[b.c0].band_rows, p.max_band_ants, p.volt_format);
     HIP_TRY(moff::launch_rows(b.n, p.n_pol, moff::ROW_MODE_FFT, false, a, a.n_bands * tgroups, lds, st), "row fft");
   }
+  // samples spread over the second grid dimension (at most 65535 workgroups there; each workgroup then transforms
+  // its column group for a run of consecutive samples)
+  const int gridy = (int)std::min<int64_t>(n_t, 65535);
   for (const moff::Block &b : p.blocks) {
     const int W = p.chans[b.c0].cols;
     ca.c0 = b.c0;
     ca.tw = d_tw(p, b.n);
     const int grid = (b.c1 - b.c0) * (b.n / W);
-    HIP_TRY(moff::launch_cols(b.n, p.n_pol, W, moff::COL_MODE_FFT, 0, ca, grid, (int)n_t,
+    HIP_TRY(moff::launch_cols(b.n, p.n_pol, W, moff::COL_MODE_FFT, 0, ca, grid, gridy,
                               moff::cols_lds_bytes(b.n, p.n_pol, W), st),
             "column fft");
   }

@@ -119,6 +119,25 @@ def test_staged_fft_full_random_grid(n):
         assert err < 2e-6, (c, err)
 
 
+def test_staged_fft_more_samples_than_one_grid_dimension():
+    """moff_fft over 70000 samples of random 32^2 grids, more than the 65535 workgroups one launch dimension
+    holds: samples on both sides of 65535 against the oracle's direct DFT."""
+    n, T = 32, 70000
+    cfg = _small(n, C=1, A=8, T=4, disk=0.4 * n, seed=77)
+    geo, kern, volts, plan = _setup(cfg)
+    gen = torch.Generator(device=DEV).manual_seed(77)
+    buf = torch.randn(T * 2 * plan.pix_total, dtype=torch.complex64, device=DEV, generator=gen)
+    keep = [0, 1, 65534, 65535, 65536, T - 1]
+    src = buf.view(T, -1)[keep].cpu().numpy()
+    plan.fft(buf, T)
+    got = buf.view(T, -1)[keep].cpu().numpy()
+    for k, t in enumerate(keep):
+        ref = ora.efield_image(src[k].reshape(2, n, n).astype(np.complex128))
+        out = np.fft.fftshift(got[k].reshape(2, n, n), axes=(-2, -1))
+        err = np.abs(out - ref).max() / np.abs(ref).max()
+        assert err < 2e-6, (t, err)
+
+
 def test_staged_accumulate_and_readout():
     n = 64
     cfg = _small(n, C=2, A=20, T=6)
