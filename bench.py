@@ -231,7 +231,8 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true", help="run a 1 GiB device copy (PMC calibration)")
     ap.add_argument("--write-traffic", metavar="DIR", help="write profiles/traffic.json from the PMC runs under DIR")
     ap.add_argument("--calibrate-peaks", action="store_true",
-                    help="measure the FP32 vector FMA and FP16 matrix-core issue rates (moff_probe)")
+                    help="measure the FP32 vector FMA and FP16 matrix-core issue rates, the FFT stage exchanges "
+                         "and the row-to-column exchange's HBM access patterns (moff_probe)")
     ap.add_argument("--pipeline", choices=["two_pass", "stream"], default="two_pass",
                     help="row/column exchange of the fused path: two kernels through HBM, or one persistent "
                          "launch per grid size streaming through each XCD's cache")
@@ -306,6 +307,20 @@ def main():
             sec = e0.elapsed_time(e1) * 1e-3
             res[name] = {"tflops": round(flops / sec / 1e12, 1),
                          "transforms_per_s": round(flops / (5 * 256 * 8) / sec / 1e9, 3) * 1e9}
+        del data
+        # the row-to-column exchange's HBM access patterns alone, over one headline launch's 8192 channel-samples
+        # (8 GiB): the row pass's tile stores and the column pass's tile loads, 5 timed launches each
+        xbuf = torch.zeros(8192 * 2 * 65536, dtype=torch.complex64, device=dev)
+        for kind, name in ((5, "exchange_store_tbs"), (6, "exchange_load_tbs")):
+            api.probe(kind, 8192, 1, xbuf)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            moved = sum(api.probe(kind, 8192, 1, xbuf) for _ in range(5))
+            e1.record()
+            e1.synchronize()
+            sec = e0.elapsed_time(e1) * 1e-3
+            res[name] = round(moved / sec / 1e12, 3)
+            res[name.replace("_tbs", "_ms_per_launch")] = round(sec / 5 * 1e3, 3)
         print(json.dumps(res))
         return
 

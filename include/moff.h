@@ -282,6 +282,12 @@ moff_status moff_profile_read(moff_plan_t plan, int32_t kind, double *total_ms, 
  * across the lanes of a wavefront (output position n holds X[bit-reversed n]).
  * Kind 4: thread 0 of each of `blocks` workgroups writes its XCD number (hardware XCC_ID) to d_out[b] (float
  * [blocks]; iters unused but >= 1).
+ * Exchange-pattern probes (the HBM access patterns of the 256^2 dual-pol fused path's row-to-column exchange,
+ * Section 5's inter-module exchange, with no arithmetic): d_out holds `blocks` channel-samples of column-group
+ * tiles, complex float [blocks][2][32][256][8] (1 MiB each; iters unused but >= 1).  Kind 5 stores all of them in
+ * the row pass's order (workgroups of 8 rows x 32 channel-samples, non-temporal 8-byte stores); kind 6 loads them
+ * in the column pass's order (workgroups of 8 columns x 256 channel-samples, non-temporal 8-byte loads) and
+ * overwrites one element per thread with the sum of what it read.
  * Enqueues on `stream`; the caller times it.  MOFF_E_INVALID for blocks or iters < 1, a NULL d_out or an unknown
  * kind. */
 moff_status moff_probe(int32_t kind, int32_t blocks, int32_t iters, float *d_out, void *stream);

@@ -440,7 +440,9 @@ def probe(kind: int, blocks: int, iters: int, out, stream=None):
     """Enqueues a probe (``moff_probe``): kind 0 FP32 vector FMAs, kind 1 FP16 matrix-core instructions (``out`` a
     device float32 tensor of blocks x 256 elements); kinds 2 and 3 the exchange probes, 256-point transforms with
     an LDS transpose or cross-lane exchanges (``out`` a device complex64 tensor of blocks x 16 x 256 elements,
-    transformed in place).  Returns the flops it performs (5 N log2 N per transform for kinds 2 and 3)."""
+    transformed in place); kind 4 the XCD of each workgroup; kinds 5 and 6 the exchange's store and load patterns
+    over ``blocks`` channel-samples (``out`` a device complex64 tensor of blocks x 2 x 256 x 256 elements).  Returns
+    the flops it performs (5 N log2 N per transform for kinds 2 and 3), or for kinds 5 and 6 the bytes it moves."""
     import torch
     lib = _lib.load()
     if not isinstance(out, torch.Tensor) or not out.is_cuda:
@@ -451,6 +453,8 @@ def probe(kind: int, blocks: int, iters: int, out, stream=None):
         _check_buffer(out, "out", out.device, torch.complex64, blocks * 16 * 256 * 8)
     elif kind == 4:
         _check_buffer(out, "out", out.device, torch.float32, blocks * 4)
+    elif kind in (5, 6):
+        _check_buffer(out, "out", out.device, torch.complex64, blocks * 2 * 65536 * 8)
     else:
         raise ValueError(f"unknown probe kind {kind}")
     _check(lib.moff_probe(kind, blocks, iters, _ptr(out), _stream_handle(stream)), "probe")
@@ -460,6 +464,8 @@ def probe(kind: int, blocks: int, iters: int, out, stream=None):
         return blocks * 4 * iters * 4 * 16384
     if kind == 4:
         return 0
+    if kind in (5, 6):
+        return blocks * 2 * 65536 * 8
     return blocks * 16 * iters * 5 * 256 * 8
 
 

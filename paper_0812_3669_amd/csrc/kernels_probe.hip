@@ -1,6 +1,7 @@
-// Issue-rate probes: what plain FP32 vector FMAs and FP16 matrix-core instructions reach on the device, as the
-// measured ceilings beside the published peaks.  Pure arithmetic on registers; each thread writes one value so
-// that nothing is optimised away.
+// Measurement probes: what plain FP32 vector FMAs and FP16 matrix-core instructions reach on the device (the
+// measured ceilings beside the published peaks; pure arithmetic on registers, each thread writes one value so that
+// nothing is optimised away), the two exchanges between transform stages, the XCD of each workgroup, and the
+// exchange's HBM access patterns alone.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -171,6 +172,44 @@ __global__ __launch_bounds__(256) void k_probe_xcc(float *out) {
   if (threadIdx.x == 0) out[blockIdx.x] = (float)xcc_id();
 }
 
+// Exchange access patterns of the 256-point dual-pol fused path with no arithmetic (kinds 5 and 6), over `ncs`
+// channel-samples of column-group tiles [u][p][q / 8][row][q % 8] (complex float, 1 MiB per channel-sample).
+// Store pattern (the row pass's): one workgroup per (8-row band, run of 32 channel-samples); per channel-sample
+// its 16 transforms (2 pols x 8 rows) of 256 outputs, thread j of transform tr storing output q = j + 16 r, r < 16,
+// with non-temporal 8-byte stores.
+__global__ __launch_bounds__(256) void k_probe_xstore(float2 *H, int ncs) {
+  const int band = (int)(blockIdx.x % 32), run = (int)(blockIdx.x / 32);
+  const int b = threadIdx.x, tr = b / 16, p = tr / 8, row = band * 8 + tr % 8, j = b % 16;
+  const int u1 = min(ncs, run * 32 + 32);
+  for (int u = run * 32; u < u1; ++u) {
+    float2 *base = H + ((int64_t)u * 2 + p) * 65536 + row * 8;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int q = j + 16 * r;
+      store_stream(base + (q / 8) * 2048 + (q % 8), make_float2((float)u, (float)r));
+    }
+  }
+}
+
+// Load pattern (the column pass's): one workgroup per (8-column group, run of 256 channel-samples); per
+// channel-sample 2 pols x 256 rows x 8 columns with non-temporal 8-byte loads, thread (col, p, j) reading rows
+// j + 16 m.  Each thread adds what it read and writes the sum over the last element it read (its own).
+__global__ __launch_bounds__(256) void k_probe_xload(float2 *H, int ncs) {
+  const int cg = (int)(blockIdx.x % 32), run = (int)(blockIdx.x / 32);
+  const int b = threadIdx.x, col = b % 8, p = (b / 8) % 2, j = b / 16;
+  const int u0 = run * 256, u1 = min(ncs, u0 + 256);
+  float acc = 0.f;
+  for (int u = u0; u < u1; ++u) {
+    const float2 *base = H + ((int64_t)u * 2 + p) * 65536 + cg * 2048 + col;
+    float2 x[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) x[m] = load_stream(base + (j + 16 * m) * 8);
+#pragma unroll
+    for (int m = 0; m < 16; ++m) acc += x[m].x + x[m].y;
+  }
+  if (u1 > u0) H[((int64_t)(u1 - 1) * 2 + p) * 65536 + cg * 2048 + (j + 16 * 15) * 8 + col].x = acc;
+}
+
 hipError_t launch_probe(int kind, int blocks, int iters, float *out, hipStream_t st) {
   if (kind == 0)
     hipLaunchKernelGGL(k_probe_fma, dim3(blocks), dim3(256), 0, st, iters, out);
@@ -180,8 +219,14 @@ hipError_t launch_probe(int kind, int blocks, int iters, float *out, hipStream_t
     hipLaunchKernelGGL(k_probe_fft_lds, dim3(blocks), dim3(256), 0, st, iters, reinterpret_cast<float2 *>(out));
   else if (kind == 3)
     hipLaunchKernelGGL(k_probe_fft_xlane, dim3(blocks * 4), dim3(256), 0, st, iters, reinterpret_cast<float2 *>(out));
-  else
+  else if (kind == 4)
     hipLaunchKernelGGL(k_probe_xcc, dim3(blocks), dim3(256), 0, st, out);
+  else if (kind == 5)
+    hipLaunchKernelGGL(k_probe_xstore, dim3(32 * ((blocks + 31) / 32)), dim3(256), 0, st,
+                       reinterpret_cast<float2 *>(out), blocks);
+  else
+    hipLaunchKernelGGL(k_probe_xload, dim3(32 * ((blocks + 255) / 256)), dim3(256), 0, st,
+                       reinterpret_cast<float2 *>(out), blocks);
   return hipGetLastError();
 }
 

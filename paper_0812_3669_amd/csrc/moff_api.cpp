@@ -372,7 +372,7 @@ void drop_graphs(moff::Plan &p) {
 extern "C" {
 
 moff_status moff_probe(int32_t kind, int32_t blocks, int32_t iters, float *d_out, void *stream) {
-  if (kind < 0 || kind > 4 || blocks < 1 || iters < 1 || !d_out)
+  if (kind < 0 || kind > 6 || blocks < 1 || iters < 1 || !d_out)
     return set_err(MOFF_E_INVALID, "bad probe arguments");
   HIP_TRY(moff::launch_probe(kind, blocks, iters, d_out, static_cast<hipStream_t>(stream)), "probe");
   return MOFF_OK;

@@ -97,3 +97,29 @@ def test_xcd_ids():
     assert x.min() >= 0 and x.max() < 8 and len(set(x.tolist())) == 8
     same = float(np.mean(x == (np.arange(blocks) % 8)))
     print(f"XCD ids: counts {np.bincount(x, minlength=8).tolist()}, equal to b % 8 for {same:.3f} of workgroups")
+
+
+def test_exchange_pattern_probes_move_what_they_report():
+    """Kind 5 stores every element of 40 channel-samples of column-group tiles (a ragged second run of samples),
+    each value naming its channel-sample and output block (u, q // 16); kind 6 reads them all back in the column
+    pass's order, and each thread's sum over its run equals the closed form 16 (sum u + n_u (q // 16))."""
+    ncs = 40
+    buf = torch.full((ncs * 2 * 65536,), complex(-1.0, -1.0), dtype=torch.complex64, device=DEV)
+    print(f"exchange pattern probes ncs={ncs}", flush=True)
+    assert api.probe(5, ncs, 1, buf) == ncs * 2 * 65536 * 8
+    torch.cuda.synchronize()
+    h = buf.cpu().numpy().reshape(ncs, 2, 32, 256, 8)
+    u = np.arange(ncs)[:, None, None, None, None]
+    q = (np.arange(32)[:, None, None] * 8 + np.arange(8)[None, None, :])[None, None]
+    assert np.array_equal(h.real, np.broadcast_to(u, h.shape).astype(np.float32))
+    assert np.array_equal(h.imag, np.broadcast_to(q // 16, h.shape).astype(np.float32))
+    assert api.probe(6, ncs, 1, buf) == ncs * 2 * 65536 * 8
+    torch.cuda.synchronize()
+    g = buf.cpu().numpy().reshape(ncs, 2, 32, 256, 8)
+    expect = 16 * (np.arange(ncs).sum() + ncs * (q[0, 0, :, 0, :] // 16))      # [tile, col]
+    for p in range(2):
+        for j in range(16):
+            assert np.array_equal(g[ncs - 1, p, :, j + 240, :].real, expect.astype(np.float32)), (p, j)
+    # everything else is what kind 5 wrote
+    g[ncs - 1, :, :, 240:, :] = h[ncs - 1, :, :, 240:, :]
+    assert np.array_equal(g, h)

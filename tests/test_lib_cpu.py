@@ -27,7 +27,7 @@ def test_status_strings(lib):
 def test_probe_rejects_bad_arguments(lib):
     """moff_probe validates on the host before anything is enqueued (MOFF_E_INVALID = 1)."""
     out = C.c_void_p(256)   # never dereferenced: every call below fails validation
-    assert lib.moff_probe(5, 1, 1, out, None) == 1
+    assert lib.moff_probe(7, 1, 1, out, None) == 1
     assert lib.moff_probe(-1, 1, 1, out, None) == 1
     assert lib.moff_probe(0, 0, 1, out, None) == 1
     assert lib.moff_probe(1, 1, 0, out, None) == 1
