@@ -31,6 +31,10 @@ PEAK_MFMA_16 = 2.5e15          # MI355X published dense FP16 / BF16 matrix-core 
 MEASURED_FP32_FMA = 119.5e12
 MEASURED_MFMA_16 = 1290.6e12
 MEASURED_COPY = 5.08e12
+# The row-to-column exchange's own HBM access patterns alone (profiles/exchange_pattern_probe.md): the FP32 row
+# pass's tile stores and the column pass's tile loads.
+MEASURED_EXCHANGE_STORE = 5.70e12
+MEASURED_EXCHANGE_LOAD = 7.06e12
 # Matrix-core form: a 256-point transform is two radix-16 stages, each 16 complex 16-point DFTs done as real
 # GEMMs (4096 complex MACs = 32768 flops per stage), once per split product (FP16 hi/lo: 3, BF16 hi/mid/lo: 6).
 # rocprofv3 SQ_INSTS_VALU_MFMA_MOPS_F16 / _BF16 x 512 reads the same count per launch.
@@ -460,6 +464,11 @@ def main():
             "flop_per_byte": intensity, "ridge_flop_per_byte": peak / PEAK_HBM,
             "lower_roof": "hbm" if intensity * PEAK_HBM < peak else roofline["bound"],
             "attainable_tflops": attainable / 1e12, "frac_of_attainable": achieved / attainable}
+        if names[dom] == "k_rows":
+            # against what the row pass's own store pattern reaches with no arithmetic around it
+            roofline["limiter"]["exchange_pattern"] = {
+                "what": "the row pass's exchange tile stores alone (moff_probe kind 5)",
+                "value_gbs": MEASURED_EXCHANGE_STORE / 1e9, "frac": gbs / MEASURED_EXCHANGE_STORE}
     algo_flops_step = sum(T * cfg.flops_per_cs(n) for n in plan.grid_n)
     if args.workload == "headline":
         metric = "channel-samples imaged/s (N=2048, 256^2 grid), "
