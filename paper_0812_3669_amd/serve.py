@@ -68,9 +68,11 @@ class JobSpec:
         split-FP16 matrix-core GEMM; any grid size)."""
         return self.mode
 
-    def chans_per_launch(self, block: int, cap_bytes: int = 1 << 30) -> int:
-        """Channels per launch so that the row-transform buffer (block samples x channels x 2 pols x n^2 x 8 B)
-        stays under ``cap_bytes``: concurrent jobs then leave room for each other."""
+    def chans_per_launch(self, block: int, cap_bytes: int = 4 << 30) -> int:
+        """Channels per launch (at most 64) so that the row-transform buffer (block samples x channels x 2 pols x
+        n^2 x 8 B) stays under ``cap_bytes``: concurrent jobs then leave room for each other.  The column pass runs
+        one workgroup per (channel, column group), so the 4 GiB default keeps 1024 of them at 512^2 (16 channels
+        of 64 column groups), four per compute unit."""
         per = block * 2 * self.grid_n ** 2 * 8
         return int(max(1, min(self.n_chan, 64, cap_bytes // per)))
 
