@@ -170,7 +170,7 @@ def cpu_baseline(cfg, geo, kern_np, volts_dev, budget_s: float = 12.0):
 
 
 def serving_bench(args, dev):
-    """The serving trace: seeded Poisson arrivals (200 jobs/s), job shapes drawn from the serving sets, integration
+    """The serving trace: seeded Poisson arrivals (``--rate``, 200 jobs/s by default), job shapes drawn from the serving sets, integration
     lengths scaled by ``--time-scale``; p50/p99 latency (completion - arrival, queueing included) beside aggregate
     channel-samples/s.  With ``--capacity-trace`` a second trace follows at 0.7 of the measured capacity (jobs/s =
     0.7 x the first trace's channel-samples/s / the mean channel-samples per job), so that the device is not
@@ -180,6 +180,10 @@ def serving_bench(args, dev):
 
     def one(rate, seed):
         trace = serve.make_trace(seed=seed, n_jobs=args.jobs, rate=rate, time_scale=args.time_scale)
+        # memory a previous trace left in torch's caching allocator counts as free for this one
+        import gc
+        gc.collect()
+        torch.cuda.empty_cache()
         free, total = torch.cuda.mem_get_info(dev)
         budget = int(0.8 * free)
         ex = serve.GpuExecutor(dev)
@@ -195,14 +199,20 @@ def serving_bench(args, dev):
         summ.update({"arrival_rate_jobs_per_s": rate, "hbm_budget_bytes": budget, "trace_seed": seed,
                      "errors": st.errors, "plans_built": ex.plans_built, "plans_reused": ex.plans_reused})
         mean_cs = float(np.mean([j.channel_samples for j in trace]))
+        # the slowest jobs: queueing (arrival to admission, host set-up included) and running (admission to image)
+        by_id = {j.job_id: j for j in trace}
+        slow = sorted(st.times.items(), key=lambda kv: kv[1][2] - kv[1][0], reverse=True)[:5]
+        summ["slowest"] = [{"job": k, "antennas": by_id[k].n_ant, "channels": by_id[k].n_chan,
+                            "samples": by_id[k].n_time, "grid": by_id[k].grid_n, "form": by_id[k].mode,
+                            "queued_s": round(a - r, 3), "running_s": round(f - a, 3)} for k, (r, a, f) in slow]
         return summ, mean_cs
 
     import numpy as np
-    summ, mean_cs = one(200.0, 4000)
+    summ, mean_cs = one(args.rate, args.trace_seed)
     runs = [summ]
     if args.capacity_trace:
         rate = 0.7 * summ["channel_samples_per_s"] / mean_cs
-        runs.append(one(rate, 4001)[0])
+        runs.append(one(rate, args.trace_seed + 1)[0])
     head = runs[-1]
     out = {
         "metric": "p99 job latency, serving trace (continuous batching, HBM-budget admission)",
@@ -241,6 +251,8 @@ def main():
                     help="row/column exchange of the fused path: two kernels through HBM, or one persistent "
                          "launch per grid size streaming through each XCD's cache")
     ap.add_argument("--jobs", type=int, default=256, help="serving: jobs in each trace")
+    ap.add_argument("--rate", type=float, default=200.0, help="serving: arrival rate of the first trace, jobs/s")
+    ap.add_argument("--trace-seed", type=int, default=4000, help="serving: seed of the first trace")
     ap.add_argument("--time-scale", type=float, default=1.0 / 64, help="serving: integration-length factor")
     ap.add_argument("--capacity-trace", action="store_true",
                     help="serving: a second trace at 0.7 of the capacity measured on the first")

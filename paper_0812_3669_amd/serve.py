@@ -68,11 +68,10 @@ class JobSpec:
         split-FP16 matrix-core GEMM; any grid size)."""
         return self.mode
 
-    def chans_per_launch(self, block: int, cap_bytes: int = 4 << 30) -> int:
+    def chans_per_launch(self, block: int, cap_bytes: int = 1 << 30) -> int:
         """Channels per launch (at most 64) so that the row-transform buffer (block samples x channels x 2 pols x
-        n^2 x 8 B) stays under ``cap_bytes``: concurrent jobs then leave room for each other.  The column pass runs
-        one workgroup per (channel, column group), so the 4 GiB default keeps 1024 of them at 512^2 (16 channels
-        of 64 column groups), four per compute unit."""
+        n^2 x 8 B) stays under ``cap_bytes``: concurrent jobs then leave room for each other, and one launch of a
+        large job does not hold a hardware queue long in front of the others' blocks."""
         per = block * 2 * self.grid_n ** 2 * 8
         return int(max(1, min(self.n_chan, 64, cap_bytes // per)))
 
@@ -133,6 +132,7 @@ class Stats:
     results: Dict[int, object] = field(default_factory=dict)
     errors: Dict[int, str] = field(default_factory=dict)
     order: List[int] = field(default_factory=list)      # job ids in admission order
+    times: Dict[int, tuple] = field(default_factory=dict)  # job id -> (arrival, admitted, finished), trace seconds
 
     def summary(self) -> dict:
         lat = np.array(self.latencies) if self.latencies else np.zeros(1)
@@ -153,7 +153,7 @@ class Scheduler:
         self.budget = hbm_budget
         self.max_slots = max_slots
         self.block = block
-        self.depth = depth              # time blocks a job keeps enqueued
+        self.depth = depth              # time blocks a job keeps enqueued when every slot is busy
         self.max_head_wait = max_head_wait
         self.keep = keep_results
 
@@ -189,11 +189,14 @@ class Scheduler:
             elif waiting != head_id:
                 head_since, head_id = now, waiting
             st.peak_concurrent = max(st.peak_concurrent, len(active))
-            # advance every active job on its own completions
+            # advance every active job on its own completions; with few jobs running each keeps up to twice as
+            # many blocks enqueued (they share its voltage buffer in stream order, so depth costs no memory; more
+            # would hold the hardware queues that other jobs' streams share)
+            depth = min(2 * self.depth, max(self.depth, -(-self.max_slots * self.depth // max(len(active), 1))))
             for js in list(active):
                 try:
                     ex.poll(js.handle)
-                    while js.enqueued < js.spec.n_time and ex.in_flight(js.handle) < self.depth:
+                    while js.enqueued < js.spec.n_time and ex.in_flight(js.handle) < depth:
                         nt = min(self.block, js.spec.n_time - js.enqueued)
                         ex.step(js.handle, js.enqueued, nt)
                         js.enqueued += nt
@@ -202,6 +205,7 @@ class Scheduler:
                         img = ex.finish(js.handle)
                         js.finished = ex.now() - t_start
                         st.latencies.append(js.finished - js.spec.arrival)
+                        st.times[js.spec.job_id] = (js.spec.arrival, js.admitted, js.finished)
                         st.channel_samples += js.spec.channel_samples
                         if self.keep:
                             st.results[js.spec.job_id] = img
@@ -381,6 +385,7 @@ class GpuExecutor:
         self._sites = {}          # array shape -> future of the instrument (geometry, gains, kernels)
         self._site_dev = {}       # array shape -> [device kernels, active users]
         self._idle = {}           # plan key -> unbound plans of finished jobs
+        self._models = {}         # job id -> future of (sky, host voltage-model response)
         self.idle_per_shape = idle_per_shape
         self.plans_built = 0
         self.plans_reused = 0
@@ -447,16 +452,26 @@ class GpuExecutor:
             if len(idle) < self.idle_per_shape:
                 idle.append(plan)
 
+    def _voltage_model(self, spec):
+        """The job's sky and the host side of its voltage generator (numpy, released interpreter lock): built on a
+        worker thread when the job arrives, so admission does not stall the loop that feeds the running jobs."""
+        from . import synth
+        site = self._site(spec)
+        cfg = spec.config()
+        sk = synth.sky(cfg)
+        return sk, synth.source_response(cfg, site["geo"], site["g"], sk)
+
     def prefetch(self, spec, block):
         with self._lock:
             if spec.job_id not in self._plans:
                 fut = self._pool.submit(self._prepare, spec, block)
                 fut.block = block
                 self._plans[spec.job_id] = fut
+                self._models[spec.job_id] = self._pool.submit(self._voltage_model, spec)
 
     def ready(self, spec):
-        fut = self._plans.get(spec.job_id)
-        return fut is not None and fut.done()
+        fut, mod = self._plans.get(spec.job_id), self._models.get(spec.job_id)
+        return fut is not None and fut.done() and mod is not None and mod.done()
 
     def _plan(self, spec, block):
         self.prefetch(spec, block)
@@ -471,6 +486,7 @@ class GpuExecutor:
         return int(plan.workspace_bytes + plan.acc_bytes + plan.image_bytes + kern + volt)
 
     def discard(self, spec):
+        self._models.pop(spec.job_id, None)
         fut = self._plans.pop(spec.job_id, None)
         if fut is not None and fut.done() and fut.exception() is None:
             self._keep(spec, getattr(fut, "block", 64), fut.result())
@@ -481,7 +497,8 @@ class GpuExecutor:
         site = self._site(spec)
         plan = self._plan(spec, block)
         cfg = spec.config()
-        sk = synth.sky(cfg)
+        self.prefetch(spec, block)
+        sk, resp = self._models.pop(spec.job_id).result()
         key = (spec.n_ant, spec.n_chan, spec.grid_n)
         stream = torch.cuda.Stream(device=self.device)
         with torch.cuda.stream(stream):
@@ -492,7 +509,7 @@ class GpuExecutor:
             plan.bind(self.device, stream=stream)
             plan.set_kernels(dev[0], stream=stream)
             acc = plan.new_accumulator()
-            gen = synth.DeviceVoltages(cfg, site["geo"], site["g"], sk, self.device, chunk=block)
+            gen = synth.DeviceVoltages(cfg, site["geo"], site["g"], sk, self.device, chunk=block, resp=resp)
             vbuf = torch.empty((block, cfg.n_chan, cfg.n_ant, cfg.n_pol, 2), dtype=torch.int8, device=self.device)
         return {"spec": spec, "plan": plan, "acc": acc, "gen": gen, "vbuf": vbuf, "stream": stream,
                 "events": deque(), "site_key": key, "block": block}

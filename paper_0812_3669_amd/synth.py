@@ -136,6 +136,13 @@ def voltages_host(cfg: Config, geo: Geometry, g: np.ndarray, sk: Sky, n_time: Op
     return q
 
 
+def source_response(cfg: Config, geo: Geometry, g: np.ndarray, sk: Sky) -> np.ndarray:
+    """Per-(channel, antenna, source, pol) response of the voltage model with conj(g) folded in, complex64
+    [C, A, S, P] (host side of ``DeviceVoltages``; it can be built ahead of the device generator)."""
+    ph = _source_phases(geo, sk) * np.sqrt(sk.flux / cfg.n_pol)[None, None, :]
+    return (ph[:, :, :, None] * np.conj(g)[None, :, None, :]).astype(np.complex64)
+
+
 class DeviceVoltages:
     """int8 voltages drawn on a torch device, chunk by chunk in time, from the same model.
 
@@ -143,14 +150,14 @@ class DeviceVoltages:
     so any chunk can be redrawn alone.  Output layout int8 [T, C, A, P, 2].
     """
 
-    def __init__(self, cfg: Config, geo: Geometry, g: np.ndarray, sk: Sky, device, chunk: int = 64):
+    def __init__(self, cfg: Config, geo: Geometry, g: np.ndarray, sk: Sky, device, chunk: int = 64,
+                 resp: Optional[np.ndarray] = None):
         import torch
         self.torch = torch
         self.cfg, self.device, self.chunk = cfg, device, chunk
-        ph = _source_phases(geo, sk) * np.sqrt(sk.flux / cfg.n_pol)[None, None, :]
-        # fold conj(g) into the per-(c, a, s, p) source response
-        resp = ph[:, :, :, None] * np.conj(g)[None, :, None, :]                   # [C, A, S, P]
-        self.resp = torch.from_numpy(resp.astype(np.complex64)).to(device)
+        if resp is None:
+            resp = source_response(cfg, geo, g, sk)
+        self.resp = torch.from_numpy(resp).to(device)
         self.alpha = quant_scale(cfg, sk)
         self.C, self.A, self.S, self.P = resp.shape[0], resp.shape[1], resp.shape[2], resp.shape[3]
 

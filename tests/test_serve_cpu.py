@@ -63,7 +63,7 @@ def test_job_site_shared_by_shape_and_launch_cap():
     big = serve.JobSpec(2, 0.0, 8192, 256, 1024, 512, "split_fp16")
     assert big.fft_mode == "split_fp16" and a.fft_mode == "split_fp16"
     cpl = big.chans_per_launch(64)
-    assert cpl == 16 and 64 * cpl * 2 * 512 ** 2 * 8 <= (4 << 30)
+    assert cpl == 4 and 64 * cpl * 2 * 512 ** 2 * 8 <= (1 << 30)
 
 
 def test_gpu_executor_prepares_jobs_in_background():
