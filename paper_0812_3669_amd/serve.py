@@ -303,6 +303,7 @@ class ModelExecutor:
         self.started: List[int] = []
         self.released: List[int] = []
         self.device_free = 0.0
+        self.max_inflight: Dict[int, int] = {}    # job id -> most blocks it had enqueued at once
 
     def _maybe_fail(self, spec, where):
         if self.fail.get(spec.job_id) == where:
@@ -341,6 +342,8 @@ class ModelExecutor:
         begin = max(self.device_free, self.t)
         self.device_free = begin + cost
         h["inflight"].append(self.device_free)
+        h["max_inflight"] = max(h.get("max_inflight", 0), len(h["inflight"]))
+        self.max_inflight[h["spec"].job_id] = h["max_inflight"]
 
     def poll(self, h):
         while h["inflight"] and h["inflight"][0] <= self.t:

@@ -142,3 +142,17 @@ def test_failed_jobs_release_their_memory_and_serving_continues():
     assert set(st.errors) == {1, 3, 4, 6}
     assert sorted(ex.released) == [4, 6]
     assert "step" in st.errors[4]
+
+
+def test_depth_doubles_only_while_slots_are_free():
+    """A job running alone keeps up to twice the block depth enqueued; with every slot busy each keeps the
+    configured depth (more would hold the hardware queues other jobs' streams share)."""
+    alone = serve.JobSpec(0, 0.0, 256, 16, 64 * 20, 128, "fp32")
+    ex = ModelExecutor()
+    Scheduler(ex, hbm_budget=1 << 40, max_slots=4, block=64, depth=2).run([alone], realtime=False)
+    assert ex.max_inflight[0] == 4
+    busy = [serve.JobSpec(j, 0.0, 256, 16, 64 * 20, 128, "fp32") for j in range(4)]
+    ex = ModelExecutor()
+    Scheduler(ex, hbm_budget=1 << 40, max_slots=4, block=64, depth=2).run(busy, realtime=False)
+    # while all four run each keeps two; the last one left alone may go to four
+    assert all(ex.max_inflight[j] <= 4 for j in range(4)) and min(ex.max_inflight.values()) == 2
