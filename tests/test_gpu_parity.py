@@ -420,6 +420,31 @@ def test_per_channel_grid_sizes_against_oracle():
     _check_images(imgs, ref, label="per-channel sizes")
 
 
+@pytest.mark.parametrize("fft", [api.FFT_FP32, api.FFT_GEMM_FP16])
+def test_interleaved_grid_sizes_fused_and_staged(fft):
+    """Grid sizes chosen per channel and interleaved (96, 256, 96, 192, 192, 128, 256): seven channels make six
+    launch blocks of consecutive equal sizes.  The fused path against the oracle pixel by pixel, and the staged
+    chain (grid, 2-D FFT, accumulate) against the fused accumulator."""
+    cfg = _small(96, C=7, A=36, T=11, disk=50.0, seed=23)
+    geo, kern, volts = synth.workload(cfg)
+    sizes = np.array([96, 256, 96, 192, 192, 128, 256], dtype=np.int32)
+    geo = synth.Geometry(geo.ant_xy_m, geo.freqs_hz, sizes, geo.cell_lambda, geo.ksize)
+    plan = api.plan_for(cfg, geo, fft_mode=fft).bind(DEV)
+    assert list(plan.grid_n) == sizes.tolist()
+    plan.set_kernels(torch.from_numpy(kern).to(DEV))
+    imgs, acc_f = _run_fused(plan, volts)
+    ref = ora.image(volts, kern, geo.ant_xy_m, geo.freqs_hz, geo.grid_n, cfg.cell_lambda)
+    _check_images(imgs, ref, label=f"interleaved sizes fft={fft}")
+    if fft == api.FFT_FP32:
+        v = torch.from_numpy(volts).to(DEV)
+        g = plan.grid(v)
+        plan.fft(g, cfg.n_time)
+        acc_s = plan.new_accumulator()
+        plan.accumulate(g, cfg.n_time, acc_s)
+        a, b = acc_s.cpu().numpy(), acc_f.cpu().numpy()
+        assert np.abs(a - b).max() <= 1e-5 * np.abs(a).max()
+
+
 def test_graph_replay_shapes_and_autotune():
     cfg = _small(128, C=5, A=64, T=40)
     geo, kern, volts, plan = _setup(cfg)
