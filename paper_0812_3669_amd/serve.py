@@ -500,8 +500,8 @@ class GpuExecutor:
         site = self._site(spec)
         plan = self._plan(spec, block)
         cfg = spec.config()
-        self.prefetch(spec, block)
-        sk, resp = self._models.pop(spec.job_id).result()
+        mod = self._models.pop(spec.job_id, None)
+        sk, resp = mod.result() if mod is not None else self._voltage_model(spec)
         key = (spec.n_ant, spec.n_chan, spec.grid_n)
         stream = torch.cuda.Stream(device=self.device)
         with torch.cuda.stream(stream):
