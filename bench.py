@@ -170,9 +170,9 @@ def cpu_baseline(cfg, geo, kern_np, volts_dev, budget_s: float = 12.0):
 
 
 def serving_bench(args, dev):
-    """The serving trace: seeded Poisson arrivals (``--rate``, 200 jobs/s by default), job shapes drawn from the serving sets, integration
-    lengths scaled by ``--time-scale``; p50/p99 latency (completion - arrival, queueing included) beside aggregate
-    channel-samples/s.  With ``--capacity-trace`` a second trace follows at 0.7 of the measured capacity (jobs/s =
+    """The serving trace: seeded Poisson arrivals (``--rate``, 200 jobs/s by default), job shapes drawn from the
+    serving sets, integration lengths scaled by ``--time-scale``; p50/p99 latency (completion - arrival, queueing
+    included) beside aggregate channel-samples/s.  With ``--capacity-trace`` a second trace follows at 0.7 of the measured capacity (jobs/s =
     0.7 x the first trace's channel-samples/s / the mean channel-samples per job), so that the device is not
     saturated and latency reflects service rather than the backlog of a burst."""
     import torch
@@ -481,6 +481,13 @@ def main():
             roofline["limiter"]["exchange_pattern"] = {
                 "what": "the row pass's exchange tile stores alone (moff_probe kind 5)",
                 "value_gbs": MEASURED_EXCHANGE_STORE / 1e9, "frac": gbs / MEASURED_EXCHANGE_STORE}
+            # both passes against the time their exchange traffic takes at the access patterns' own rates
+            cols_traffic = _traffic(args.fft, "k_cols", launch_cs)
+            if 1 in kt and cols_traffic:
+                pair_ms = avg_ms + kt[1]["ms"] / max(kt[1]["launches"], 1)
+                floor_ms = (traffic / MEASURED_EXCHANGE_STORE + cols_traffic / MEASURED_EXCHANGE_LOAD) * 1e3
+                roofline["limiter"]["two_pass_exchange_floor"] = {
+                    "floor_ms_per_launch": floor_ms, "measured_ms_per_launch": pair_ms, "frac": floor_ms / pair_ms}
     algo_flops_step = sum(T * cfg.flops_per_cs(n) for n in plan.grid_n)
     if args.workload == "headline":
         metric = "channel-samples imaged/s (N=2048, 256^2 grid), "
