@@ -29,7 +29,7 @@ PEAK_MFMA_16 = 2.5e15          # MI355X published dense FP16 / BF16 matrix-core 
 # FMA issue rate of this build (packed FP32 disabled), the FP16 matrix-core instruction rate, and a plain 1 GiB
 # device copy (read + write).
 MEASURED_FP32_FMA = 119.5e12
-MEASURED_MFMA_16 = 1290.6e12
+MEASURED_MFMA_16 = 1984.6e12
 MEASURED_COPY = 5.08e12
 # The row-to-column exchange's own HBM access patterns alone (profiles/exchange_pattern_probe.md): the FP32 row
 # pass's tile stores and the column pass's tile loads.

@@ -45,8 +45,12 @@ __global__ __launch_bounds__(256) void k_probe_mfma(int iters, float *out) {
   probe_float4 acc[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) acc[k] = probe_float4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
-  for (int i = 0; i < iters; ++i) {
+  // two iterations per trip (8 instructions back to back), then the odd one
+  for (int i = 0; i + 1 < iters; i += 2) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc[k & 3] = __builtin_amdgcn_mfma_f32_16x16x32_f16(x, y, acc[k & 3], 0, 0, 0);
+  }
+  if (iters & 1) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) acc[k] = __builtin_amdgcn_mfma_f32_16x16x32_f16(x, y, acc[k], 0, 0, 0);
   }
