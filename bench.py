@@ -187,7 +187,7 @@ def serving_bench(args, dev):
         free, total = torch.cuda.mem_get_info(dev)
         budget = int(0.8 * free)
         ex = serve.GpuExecutor(dev)
-        sch = serve.Scheduler(ex, hbm_budget=budget, max_slots=8, block=64,
+        sch = serve.Scheduler(ex, hbm_budget=budget, max_slots=args.serve_slots, block=args.serve_block,
                               progress=lambda k, n: print(f"bench: {k}/{n} jobs done", file=sys.stderr, flush=True)
                               if k % 16 == 0 or k == n else None)
         print(f"bench: serving {len(trace)} jobs at {rate:.3g} jobs/s, HBM budget {budget / 2**30:.1f} GiB",
@@ -222,7 +222,8 @@ def serving_bench(args, dev):
         "data": "synthetic (seeded point sources + noise, int8 voltages)",
         "config": {"workload": "serving: Poisson arrivals, %d jobs per trace, antennas {256,1024,4096,8192}, channels "
                                "{16,64,256}, samples {1k,8k,64k} x %.4g, grids {128,256,512}, fp32 or split_fp16, "
-                               "64-sample blocks, 8 slots, 2 blocks in flight per job" % (args.jobs, args.time_scale)},
+                               "%d-sample blocks, %d slots, 2 blocks in flight per job (4 while slots are free)"
+                               % (args.jobs, args.time_scale, args.serve_block, args.serve_slots)},
         "serving": runs,
     }
     print(json.dumps(out))
@@ -253,6 +254,8 @@ def main():
     ap.add_argument("--jobs", type=int, default=256, help="serving: jobs in each trace")
     ap.add_argument("--rate", type=float, default=200.0, help="serving: arrival rate of the first trace, jobs/s")
     ap.add_argument("--trace-seed", type=int, default=4000, help="serving: seed of the first trace")
+    ap.add_argument("--serve-block", type=int, default=64, help="serving: samples per block")
+    ap.add_argument("--serve-slots", type=int, default=8, help="serving: jobs admitted at once")
     ap.add_argument("--time-scale", type=float, default=1.0 / 64, help="serving: integration-length factor")
     ap.add_argument("--capacity-trace", action="store_true",
                     help="serving: a second trace at 0.7 of the capacity measured on the first")
